@@ -1,0 +1,206 @@
+/*
+ * hvox.h -- C ABI of the MI355X (gfx950) HVOX library.
+ *
+ * HVOX (Kashani, Rue Queralt, Jarret, Simeoni, arXiv 2306.06007) evaluates
+ * interferometric synthesis and its adjoint with a chunked 3D type-3 NUFFT.
+ * The problem statement (Sect. 2, Eqs. 2-3, unit tesselation weights):
+ *
+ *   hvox_synthesis  (sky -> vis):  V_k = sum_n I_n exp(-2 pi i <p_k, r_n>)
+ *   hvox_analysis   (vis -> sky):  I_n = sum_k V_k exp(+2 pi i <p_k, r_n>)
+ *
+ * p_k are uvw baselines in wavelengths, r_n points of an arbitrary sky mesh
+ * (unit vectors; any finite 3-vectors are accepted).  The paper names the
+ * sky->vis direction "analysis" (Eq. 2) and vis->sky "synthesis" (Eq. 3);
+ * this library follows the names above and states each direction explicitly.
+ *
+ * Both sums are approximated to relative l2 accuracy eps (Sect. 3: the
+ * NUFFT's error is controlled through the kernel support) by partitioning the
+ * visibility and sky domains into chunks (Sect. 3.1, Eq. 8; Sect. 3.2,
+ * Algorithms 1-2) and evaluating every (sky chunk, visibility chunk)
+ * sub-problem either as a type-3 NUFFT (spread, 3D FFT, interpolate,
+ * deconvolve; Sect. 3) or by direct summation (Sect. 3.1, last bullet).
+ *
+ * Conventions shared by every entry point
+ *  - Coordinates are host arrays of float64, row-major [n][3]; they are
+ *    copied, the plan keeps no caller pointer.
+ *  - Data vectors are DEVICE pointers to interleaved complex values, complex64
+ *    for HVOX_F32 plans and complex128 for HVOX_F64 plans, laid out as ntrans
+ *    contiguous rows: sky is [ntrans][n_pix], vis is [ntrans][n_vis].
+ *  - Outputs are overwritten, never accumulated into.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream)
+ *    and the call returns once it is enqueued.  A plan is immutable after
+ *    creation, but owns one workspace: at most one call per plan may be in
+ *    flight at a time; concurrent work needs distinct plans.
+ *  - Every call returns 0 on success or a negative hvox error code; no C++
+ *    exception crosses this boundary.  hvox_last_error() gives a message
+ *    (thread-local) describing the most recent failure of this thread.
+ */
+#ifndef HVOX_H
+#define HVOX_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HVOX_VERSION 100
+
+/* error codes */
+#define HVOX_OK          0
+#define HVOX_ERR_ARG    (-1)  /* NULL pointer, negative size, ntrans < 1, non-finite coordinate, bad option */
+#define HVOX_ERR_EPS    (-2)  /* eps < 0, or below the floor of the dtype / upsampling factor */
+#define HVOX_ERR_OOM    (-3)  /* device allocation failed or the workspace would exceed its cap */
+#define HVOX_ERR_HIP    (-4)  /* a HIP runtime call failed (message in hvox_last_error) */
+#define HVOX_ERR_STATE  (-5)  /* freed / host-only plan used for a transform, or wrong call sequence */
+
+typedef enum { HVOX_F32 = 0, HVOX_F64 = 1 } hvox_dtype;
+
+/* option flags */
+#define HVOX_REAL_SKY        0x1  /* analysis returns Re(A^H V) (imaginary part 0): a real-valued adjoint
+                                     for real sky maps (Sect. 4, the `real` option of Listing 1) */
+#define HVOX_PLAN_HOST_ONLY  0x2  /* plan on the host only (partition, pair sizes, costs); no device memory,
+                                     transforms return HVOX_ERR_STATE.  For inspection and CPU tests */
+#define HVOX_TIMING          0x4  /* record HIP events around every kernel launch; see hvox_stats */
+
+typedef struct hvox_plan_s *hvox_plan_t;
+
+/* Plan options.  A zero-initialised struct (or a NULL pointer) selects the
+ * defaults noted on each field. */
+typedef struct {
+    double max_fft_bytes;     /* FFT memory budget B per sub-problem, bytes (Sect. 3.2, Algorithm 1).
+                                 0 -> 500e6 (the paper's default partition size, Table 2);
+                                 +INFINITY -> one chunk per domain (monolithic type-3, Sect. 3). */
+    double anisotropy;        /* alpha >= 1 of Algorithm 1; 0 -> 1. */
+    double upsampfac;         /* sigma, the grid upsampling factor; 0 -> 1.25 (the type-3 default
+                                 discussed in Sect. 5.2).  Accepted range [1.25, 2]. */
+    double direct_threshold;  /* per-sub-problem choice between NUFFT and direct summation (Sect. 3.1):
+                                 < 0  -> automatic (cost model);  0 -> never direct (forced NUFFT);
+                                 +INFINITY -> always direct.  A positive finite value t makes a
+                                 sub-problem direct when t * cost_direct <= cost_nufft. */
+    double workspace_bytes;   /* cap on the workspace shared by concurrently executed sub-problems;
+                                 0 -> 4 GiB (raised to the largest single sub-problem if needed). */
+    const int32_t *vis_chunk; /* optional custom partition (host, [n_vis] chunk ids >= 0), replacing
+                                 Algorithm 2 on the visibility domain (Sect. 4, allocate()). */
+    const int32_t *sky_chunk; /* same for the sky domain ([n_pix]). */
+    int32_t flags;            /* HVOX_REAL_SKY | HVOX_PLAN_HOST_ONLY | HVOX_TIMING */
+    int32_t reserved;
+} hvox_opts;
+
+/* What a plan decided.  Sizes in bytes; counts of sub-problems are per
+ * direction (the same (sky chunk, vis chunk) set serves both). */
+typedef struct {
+    int64_t n_vis, n_pix;
+    int32_t dtype;            /* hvox_dtype */
+    int32_t w;                /* kernel support (grid cells per dimension) */
+    double  beta;             /* exponential-of-semicircle shape parameter */
+    double  sigma;            /* upsampling factor */
+    double  eps;              /* requested accuracy */
+    double  h[3], eta[3];     /* Algorithm 1 maximum box dimensions (visibility, sky) */
+    int32_t n_vis_chunks, n_sky_chunks;
+    int64_t n_pairs_nufft, n_pairs_direct;
+    int64_t n_batches;        /* groups of NUFFT sub-problems sharing the workspace */
+    int64_t resident_bytes;   /* device memory held by the plan besides the workspace */
+    int64_t workspace_bytes;  /* device workspace (grids of concurrently executed sub-problems) */
+    int64_t max_pair_workspace_bytes;
+    double  grid_cells;       /* sum over NUFFT sub-problems of the grid-1 cell counts */
+    double  direct_terms;     /* sum over direct sub-problems of N_src * N_tgt */
+    double  est_seconds;      /* cost-model estimate of one synthesis + one analysis */
+    double  plan_seconds;     /* host + device time spent in hvox_plan */
+} hvox_plan_info_t;
+
+/* Per-kernel statistics of the calls since the last reset (HVOX_TIMING plans). */
+#define HVOX_K_ZERO     0
+#define HVOX_K_SPREAD   1
+#define HVOX_K_FFT_X    2
+#define HVOX_K_FFT_Y    3
+#define HVOX_K_FFT_Z    4
+#define HVOX_K_INTERP   5
+#define HVOX_K_DIRECT   6
+#define HVOX_K_FINAL    7
+#define HVOX_K_COUNT    8
+typedef struct {
+    int64_t launches[HVOX_K_COUNT];
+    double  ms[HVOX_K_COUNT];           /* summed HIP-event durations */
+    double  alg_bytes[HVOX_K_COUNT];    /* algorithmic HBM bytes moved (see the kernel documentation) */
+    double  alg_flops[HVOX_K_COUNT];    /* algorithmic arithmetic (direct: terms) */
+} hvox_stats_t;
+
+/*
+ * Create a plan for uvw [n_vis][3] (host, wavelengths) and xyz [n_pix][3]
+ * (host, sky points) at accuracy eps for data of the given dtype.
+ * Host work: boxes, kernel parameters, Algorithm 1 (maximum Heisenberg box
+ * dimensions under the FFT budget, Sect. 3.2), Algorithm 2 on both domains,
+ * chunk-order permutations (Sect. 4: inputs are re-ordered so that chunks are
+ * contiguous), per-sub-problem sizes and NUFFT-or-direct choice.  Device work
+ * (on `stream`, synchronised before return): coordinates, permutations,
+ * deconvolution and FFT tables.
+ * eps == 0 selects direct summation for every sub-problem (the paper's eps=0
+ * case).  eps floors: 1e-6 for HVOX_F32, 1e-10 for HVOX_F64.
+ * n_vis or n_pix may be 0 (outputs are then all zero / empty).
+ * On success *out receives the plan, owned by the caller (hvox_free).
+ */
+int hvox_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t n_pix,
+              double eps, int32_t dtype, const hvox_opts *opts, void *stream,
+              hvox_plan_t *out);
+
+/* sky -> vis:  vis[t][k] = sum_n sky[t][n] exp(-2 pi i <p_k, r_n>)   (Eq. 2)
+ * sky: device [ntrans][n_pix] complex, vis: device [ntrans][n_vis] complex. */
+int hvox_synthesis(hvox_plan_t plan, const void *sky, void *vis, int32_t ntrans, void *stream);
+
+/* vis -> sky:  sky[t][n] = sum_k vis[t][k] exp(+2 pi i <p_k, r_n>)   (Eq. 3, the adjoint)
+ * With HVOX_REAL_SKY the imaginary part of sky is set to 0. */
+int hvox_analysis(hvox_plan_t plan, const void *vis, void *sky, int32_t ntrans, void *stream);
+
+/* Release every resource of the plan (device memory after synchronising the
+ * plan's last stream).  NULL is a no-op. */
+int hvox_free(hvox_plan_t plan);
+
+/* Fill *out with the plan's decisions and memory footprint. */
+int hvox_plan_info(hvox_plan_t plan, hvox_plan_info_t *out);
+
+/* Chunk-order permutations (Sect. 4): vis_perm[j] is the user index of the
+ * j-th visibility in chunk order, likewise sky_perm.  Host arrays of n_vis and
+ * n_pix entries; either pointer may be NULL.  Supplying data already in this
+ * order is what the paper recommends for repeated transforms. */
+int hvox_plan_permutation(hvox_plan_t plan, int32_t *vis_perm, int32_t *sky_perm);
+
+/* Chunk id of every point in user order (host arrays, either may be NULL). */
+int hvox_plan_chunks(hvox_plan_t plan, int32_t *vis_chunk, int32_t *sky_chunk);
+
+/* Kernel statistics of an HVOX_TIMING plan; hvox_stats_reset clears them.
+ * Synchronises the plan's last stream. */
+int hvox_stats(hvox_plan_t plan, hvox_stats_t *out);
+int hvox_stats_reset(hvox_plan_t plan);
+
+/* ---- host-only helpers (no GPU needed) --------------------------------- */
+
+/* Kernel parameters for accuracy eps at upsampling sigma: support w (cells)
+ * and shape beta of the exponential-of-semicircle kernel
+ * ES(z) = exp(beta (sqrt(1 - z^2) - 1)), |z| < 1 (the ES kernel named in
+ * Sect. 2.1). */
+int hvox_kernel_params(double eps, double sigma, int32_t *w, double *beta);
+
+/* Algorithm 1 (Sect. 3.2): maximum box dimensions h (visibility) and eta
+ * (sky) minimising the chunk count prod(B/h) prod(P/eta) subject to
+ * prod(h eta) <= v_max, h <= B, eta <= P and the anisotropy bounds alpha.
+ * B, P: full widths of the two domains (zero widths are floored so that the
+ * dimension spans one grid cell). */
+int hvox_alg1(const double B[3], const double P[3], double v_max, double alpha,
+              double h[3], double eta[3]);
+
+/* Algorithm 2 (Sect. 3.2): partition points x [n][3] (host) into chunks whose
+ * boxes are at most h per dimension.  labels[n] receives chunk ids numbered
+ * 0..n_chunks-1.  Returns the number of chunks (>= 0) or an error code. */
+int64_t hvox_partition(const double *x, int64_t n, const double h[3], int32_t *labels);
+
+/* Human-readable text of an error code, and the calling thread's last message. */
+const char *hvox_error_string(int code);
+const char *hvox_last_error(void);
+int hvox_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HVOX_H */

@@ -1,0 +1,664 @@
+// C ABI of the HVOX library (include/hvox.h): plan creation (host planner +
+// device uploads), the stream-ordered executor of synthesis / analysis, and
+// per-kernel HIP-event statistics.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hvox_internal.hpp"
+
+namespace hvox {
+
+hipError_t launch_zero(double *p, int64_t n, hipStream_t st);
+hipError_t launch_deconv(const double *xyz, int64_t n, const int32_t *chunk_of, const double *ctr,
+                         const double *hscale, const double *zq, const double *aq, int nq, int w, double *out,
+                         hipStream_t st);
+template <typename T>
+hipError_t launch_spread(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t, const int32_t *,
+                         const void *, void *, int, double, double, hipStream_t);
+template <typename T>
+hipError_t launch_fft(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *, const double *, int,
+                      double, hipStream_t);
+template <typename T>
+hipError_t launch_interp(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t, const double *,
+                         const void *, double *, int, double, double, hipStream_t);
+template <typename T>
+hipError_t launch_direct(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
+                         const int32_t *, const void *, double *, double, hipStream_t);
+template <typename T>
+hipError_t launch_finalize(const double *, int64_t, const int32_t *, void *, int, hipStream_t);
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+struct DevDir {
+    PairDev *pairs = nullptr;
+    int64_t *pre_pts = nullptr, *pre_tgts = nullptr, *pre_tiles[3] = {nullptr, nullptr, nullptr};
+    DirectItem *direct = nullptr;
+    double *deconv = nullptr;        // per chunk-order target
+};
+
+struct TimedLaunch {
+    int kind;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+}  // namespace hvox
+
+struct hvox_plan_s {
+    hvox::HostPlan hp;
+    bool host_only = false;
+    int device = 0;
+    size_t resident_bytes = 0;
+    std::vector<void *> allocations;
+    double *vis_xyz = nullptr, *sky_xyz = nullptr;     // SoA [3][n], chunk order
+    int32_t *vis_perm = nullptr, *sky_perm = nullptr;
+    double *precor = nullptr;
+    void *tw = nullptr;
+    hvox::DevDir syn, ana;
+    void *ws = nullptr;
+    double *acc = nullptr;
+    hipStream_t last_stream = nullptr;
+    double plan_seconds = 0.0;
+    // timing
+    std::vector<hvox::TimedLaunch> pending;
+    std::vector<hipEvent_t> spare_events;
+    hvox_stats_t stats{};
+};
+
+namespace hvox {
+namespace {
+
+template <typename V>
+hipError_t upload(hvox_plan_s *pl, const std::vector<V> &v, V **dst, hipStream_t st)
+{
+    *dst = nullptr;
+    if (v.empty()) return hipSuccess;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, v.size() * sizeof(V));
+    if (e != hipSuccess) return e;
+    pl->allocations.push_back(p);
+    pl->resident_bytes += v.size() * sizeof(V);
+    *dst = static_cast<V *>(p);
+    return hipMemcpyAsync(p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, st);
+}
+
+hipError_t dev_alloc(hvox_plan_s *pl, size_t bytes, void **dst, bool resident)
+{
+    *dst = nullptr;
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMalloc(dst, bytes);
+    if (e != hipSuccess) return e;
+    pl->allocations.push_back(*dst);
+    if (resident) pl->resident_bytes += bytes;
+    return hipSuccess;
+}
+
+void release(hvox_plan_s *pl)
+{
+    for (void *p : pl->allocations) (void)hipFree(p);
+    pl->allocations.clear();
+    for (auto &t : pl->pending) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
+    pl->pending.clear();
+    for (hipEvent_t e : pl->spare_events) (void)hipEventDestroy(e);
+    pl->spare_events.clear();
+}
+
+std::vector<double> soa(const std::vector<double> &aos, const std::vector<int32_t> &perm)
+{
+    const size_t n = perm.size();
+    std::vector<double> out(3 * n);
+    for (size_t j = 0; j < n; ++j)
+        for (int d = 0; d < 3; ++d) out[d * n + j] = aos[3 * static_cast<size_t>(perm[j]) + d];
+    return out;
+}
+
+std::vector<int32_t> chunk_of_order(const ChunkSet &cs)
+{
+    std::vector<int32_t> out(cs.n);
+    for (int32_t c = 0; c < cs.nc; ++c)
+        for (int64_t j = cs.off[c]; j < cs.off[c + 1]; ++j) out[j] = c;
+    return out;
+}
+
+// ---- timing -----------------------------------------------------------------
+hipEvent_t take_event(hvox_plan_s *pl)
+{
+    if (!pl->spare_events.empty()) {
+        hipEvent_t e = pl->spare_events.back();
+        pl->spare_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+hipError_t resolve_timing(hvox_plan_s *pl)
+{
+    for (auto &t : pl->pending) {
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e != hipSuccess) return e;
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, t.a, t.b);
+        if (e != hipSuccess) return e;
+        pl->stats.ms[t.kind] += ms;
+        pl->spare_events.push_back(t.a);
+        pl->spare_events.push_back(t.b);
+    }
+    pl->pending.clear();
+    return hipSuccess;
+}
+
+template <class F>
+hipError_t timed(hvox_plan_s *pl, int kind, hipStream_t st, F &&f)
+{
+    pl->stats.launches[kind] += 1;
+    if (!(pl->hp.prm.flags & HVOX_TIMING)) return f();
+    hipEvent_t a = take_event(pl), b = take_event(pl);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, st);
+    if (e == hipSuccess) e = f();
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    pl->pending.push_back({kind, a, b});
+    if (e == hipSuccess && pl->pending.size() >= 2048) e = resolve_timing(pl);
+    return e;
+}
+
+// ---- executor -----------------------------------------------------------------
+template <typename T>
+int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, int32_t ntrans, hipStream_t st)
+{
+    const HostPlan &hp = pl->hp;
+    const Params &p = hp.prm;
+    const DirPlan &dp = synthesis ? hp.syn : hp.ana;
+    const DevDir &dd = synthesis ? pl->syn : pl->ana;
+    const int64_t n_src = synthesis ? hp.n_pix : hp.n_vis;
+    const int64_t n_tgt = synthesis ? hp.n_vis : hp.n_pix;
+    const double *sxyz = synthesis ? pl->sky_xyz : pl->vis_xyz;
+    const double *txyz = synthesis ? pl->vis_xyz : pl->sky_xyz;
+    const int32_t *sperm = synthesis ? pl->sky_perm : pl->vis_perm;
+    const int32_t *tperm = synthesis ? pl->vis_perm : pl->sky_perm;
+    const double iota = synthesis ? -1.0 : 1.0;
+    const int real_only = (!synthesis && (p.flags & HVOX_REAL_SKY)) ? 1 : 0;
+    using C = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+    hipError_t e = hipSuccess;
+#define HVOX_TRY(expr)                                                                             \
+    do {                                                                                           \
+        e = (expr);                                                                                \
+        if (e != hipSuccess) return fail(HVOX_ERR_HIP, std::string("HIP: ") + hipGetErrorString(e)); \
+    } while (0)
+
+    for (int32_t t = 0; t < ntrans; ++t) {
+        const C *in_t = static_cast<const C *>(in) + static_cast<int64_t>(t) * n_src;
+        C *out_t = static_cast<C *>(out) + static_cast<int64_t>(t) * n_tgt;
+        if (n_tgt == 0) continue;
+        HVOX_TRY(timed(pl, HVOX_K_ZERO, st, [&] { return launch_zero(pl->acc, 2 * n_tgt, st); }));
+        for (const Batch &b : dp.batches) {
+            const PairDev *pairs = dd.pairs + b.pair0;
+            const int np = static_cast<int>(b.npairs);
+            HVOX_TRY(timed(pl, HVOX_K_ZERO, st, [&] {
+                // the batch's grid-1 buffers, counted in doubles (complex = 1 or 2 doubles)
+                return launch_zero(reinterpret_cast<double *>(static_cast<C *>(pl->ws) + b.zero_off),
+                                   b.zero_cnt * static_cast<int64_t>(sizeof(C) / sizeof(double)), st);
+            }));
+            HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
+                return launch_spread<T>(pairs, dd.pre_pts + b.pre_pts, np, b.pts, sxyz, n_src, sperm, in_t, pl->ws,
+                                        p.w, p.beta, iota, st);
+            }));
+            for (int pass = 0; pass < 3; ++pass)
+                HVOX_TRY(timed(pl, HVOX_K_FFT_X + pass, st, [&] {
+                    return launch_fft<T>(pairs, dd.pre_tiles[pass] + b.pre_tiles[pass], np, b.tiles[pass], pass,
+                                         pl->ws, pl->tw, pl->precor, b.lds_elems[pass], iota, st);
+                }));
+            HVOX_TRY(timed(pl, HVOX_K_INTERP, st, [&] {
+                return launch_interp<T>(pairs, dd.pre_tgts + b.pre_tgts, np, b.tgts, txyz, n_tgt, dd.deconv, pl->ws,
+                                        pl->acc, p.w, p.beta, iota, st);
+            }));
+        }
+        if (!dp.direct.empty())
+            HVOX_TRY(timed(pl, HVOX_K_DIRECT, st, [&] {
+                return launch_direct<T>(dd.direct, static_cast<int64_t>(dp.direct.size()), sxyz, n_src, txyz, n_tgt,
+                                        sperm, in_t, pl->acc, iota, st);
+            }));
+        HVOX_TRY(timed(pl, HVOX_K_FINAL, st, [&] {
+            return launch_finalize<T>(pl->acc, n_tgt, tperm, out_t, real_only, st);
+        }));
+        for (int k = 0; k < HVOX_K_COUNT; ++k) {
+            pl->stats.alg_bytes[k] += dp.alg_bytes[k];
+            pl->stats.alg_flops[k] += dp.alg_flops[k];
+        }
+    }
+#undef HVOX_TRY
+    pl->last_stream = st;
+    return HVOX_OK;
+}
+
+int transform(hvox_plan_s *pl, bool synthesis, const void *in, void *out, int32_t ntrans, void *stream)
+{
+    if (!pl) return fail(HVOX_ERR_STATE, "NULL plan");
+    if (pl->host_only) return fail(HVOX_ERR_STATE, "host-only plan cannot run transforms");
+    if (ntrans < 1) return fail(HVOX_ERR_ARG, "ntrans must be >= 1");
+    const int64_t n_in = synthesis ? pl->hp.n_pix : pl->hp.n_vis;
+    const int64_t n_out = synthesis ? pl->hp.n_vis : pl->hp.n_pix;
+    if ((n_in > 0 && !in) || (n_out > 0 && !out)) return fail(HVOX_ERR_ARG, "NULL data pointer");
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(HVOX_ERR_HIP, "hipGetDevice failed");
+    if (cur != pl->device) return fail(HVOX_ERR_STATE, "the plan's device is not the current device");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (pl->hp.prm.dtype == HVOX_F64) return run_direction<double>(pl, synthesis, in, out, ntrans, st);
+    return run_direction<float>(pl, synthesis, in, out, ntrans, st);
+}
+
+int upload_dir(hvox_plan_s *pl, const DirPlan &dp, DevDir *dd, hipStream_t st)
+{
+    hipError_t e;
+    if ((e = upload(pl, dp.pairs, &dd->pairs, st)) != hipSuccess) return HVOX_ERR_OOM;
+    if ((e = upload(pl, dp.pre_pts, &dd->pre_pts, st)) != hipSuccess) return HVOX_ERR_OOM;
+    if ((e = upload(pl, dp.pre_tgts, &dd->pre_tgts, st)) != hipSuccess) return HVOX_ERR_OOM;
+    for (int q = 0; q < 3; ++q)
+        if ((e = upload(pl, dp.pre_tiles[q], &dd->pre_tiles[q], st)) != hipSuccess) return HVOX_ERR_OOM;
+    if ((e = upload(pl, dp.direct, &dd->direct, st)) != hipSuccess) return HVOX_ERR_OOM;
+    return HVOX_OK;
+}
+
+int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
+{
+    HostPlan &hp = pl->hp;
+    const Params &p = hp.prm;
+    if (hipGetDevice(&pl->device) != hipSuccess) { *err = "hipGetDevice failed"; return HVOX_ERR_HIP; }
+    std::vector<double> vx = soa(hp.uvw, hp.vis.perm), sx = soa(hp.xyz, hp.sky.perm);
+    int rc = HVOX_OK;
+    auto chk = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && rc == HVOX_OK) {
+            rc = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? HVOX_ERR_OOM : HVOX_ERR_HIP;
+            *err = std::string(what) + ": " + hipGetErrorString(e);
+        }
+    };
+    chk(upload(pl, vx, &pl->vis_xyz, st), "visibility coordinates");
+    chk(upload(pl, sx, &pl->sky_xyz, st), "sky coordinates");
+    chk(upload(pl, hp.vis.perm, &pl->vis_perm, st), "visibility permutation");
+    chk(upload(pl, hp.sky.perm, &pl->sky_perm, st), "sky permutation");
+    if (rc) return rc;
+
+    // pre-correction tables 1 / Phi_hat(l / n2) (Gauss-Legendre, host)
+    const int nq = 2 * p.w + 60;
+    std::vector<double> zq, wq;
+    gauss_legendre(nq, &zq, &wq);
+    std::vector<double> aq(nq);
+    for (int q = 0; q < nq; ++q) aq[q] = wq[q] * std::exp(p.beta * (std::sqrt(1.0 - zq[q] * zq[q]) - 1.0));
+    std::vector<double> precor(hp.precor_nu.size());
+    for (size_t i = 0; i < precor.size(); ++i) {
+        double s = 0.0;
+        for (int q = 0; q < nq; ++q) s += aq[q] * std::cos(M_PI * hp.precor_nu[i] * p.w * zq[q]);
+        precor[i] = 1.0 / (0.5 * p.w * s);
+    }
+    chk(upload(pl, precor, &pl->precor, st), "pre-correction tables");
+    // twiddles exp(-2 pi i j / n); the host tables stay alive until the
+    // stream synchronisation that ends the plan upload
+    std::vector<double2> tw64;
+    std::vector<float2> tw32;
+    if (p.dtype == HVOX_F64) {
+        tw64.resize(hp.tw_total);
+        for (size_t t = 0; t < hp.tw_len.size(); ++t)
+            for (int32_t j = 0; j < hp.tw_len[t]; ++j) {
+                double a = 2.0 * M_PI * j / hp.tw_len[t];
+                tw64[hp.tw_off[t] + j] = make_double2(std::cos(a), -std::sin(a));
+            }
+        double2 *d = nullptr;
+        chk(upload(pl, tw64, &d, st), "twiddles");
+        pl->tw = d;
+    } else {
+        tw32.resize(hp.tw_total);
+        for (size_t t = 0; t < hp.tw_len.size(); ++t)
+            for (int32_t j = 0; j < hp.tw_len[t]; ++j) {
+                double a = 2.0 * M_PI * j / hp.tw_len[t];
+                tw32[hp.tw_off[t] + j] = make_float2(static_cast<float>(std::cos(a)), static_cast<float>(-std::sin(a)));
+            }
+        float2 *d = nullptr;
+        chk(upload(pl, tw32, &d, st), "twiddles");
+        pl->tw = d;
+    }
+    if (rc) return rc;
+    if (upload_dir(pl, hp.syn, &pl->syn, st) || upload_dir(pl, hp.ana, &pl->ana, st)) {
+        *err = "device allocation of sub-problem tables failed";
+        return HVOX_ERR_OOM;
+    }
+
+    // deconvolution factors of every target, per direction
+    double *d_zq = nullptr, *d_aq = nullptr, *d_ctr_v = nullptr, *d_ctr_s = nullptr, *d_hs_v = nullptr,
+           *d_hs_s = nullptr;
+    int32_t *d_cov = nullptr, *d_cos = nullptr;
+    chk(upload(pl, zq, &d_zq, st), "quadrature");
+    chk(upload(pl, aq, &d_aq, st), "quadrature");
+    chk(upload(pl, hp.vis.ctr, &d_ctr_v, st), "chunk centres");
+    chk(upload(pl, hp.sky.ctr, &d_ctr_s, st), "chunk centres");
+    chk(upload(pl, hp.syn_tgt_scale, &d_hs_v, st), "target scales");
+    chk(upload(pl, hp.ana_tgt_scale, &d_hs_s, st), "target scales");
+    std::vector<int32_t> cov = chunk_of_order(hp.vis), cos_ = chunk_of_order(hp.sky);
+    chk(upload(pl, cov, &d_cov, st), "chunk ids");
+    chk(upload(pl, cos_, &d_cos, st), "chunk ids");
+    void *tmp = nullptr;
+    chk(dev_alloc(pl, sizeof(double) * hp.n_vis, &tmp, true), "deconvolution");
+    pl->syn.deconv = static_cast<double *>(tmp);
+    chk(dev_alloc(pl, sizeof(double) * hp.n_pix, &tmp, true), "deconvolution");
+    pl->ana.deconv = static_cast<double *>(tmp);
+    if (rc) return rc;
+    chk(launch_deconv(pl->vis_xyz, hp.n_vis, d_cov, d_ctr_v, d_hs_v, d_zq, d_aq, nq, p.w, pl->syn.deconv, st),
+        "deconvolution kernel");
+    chk(launch_deconv(pl->sky_xyz, hp.n_pix, d_cos, d_ctr_s, d_hs_s, d_zq, d_aq, nq, p.w, pl->ana.deconv, st),
+        "deconvolution kernel");
+    // accumulator and workspace
+    const size_t delta = p.dtype == HVOX_F64 ? 16 : 8;
+    chk(dev_alloc(pl, 16 * static_cast<size_t>(std::max(hp.n_vis, hp.n_pix)), &tmp, true), "accumulator");
+    pl->acc = static_cast<double *>(tmp);
+    chk(dev_alloc(pl, delta * static_cast<size_t>(hp.ws_elems), &pl->ws, false), "workspace");
+    if (rc) return rc;
+    chk(hipStreamSynchronize(st), "plan upload");
+    return rc;
+}
+
+}  // namespace
+}  // namespace hvox
+
+using namespace hvox;
+
+extern "C" {
+
+int hvox_version(void) { return HVOX_VERSION; }
+
+const char *hvox_error_string(int code)
+{
+    switch (code) {
+        case HVOX_OK: return "success";
+        case HVOX_ERR_ARG: return "invalid argument";
+        case HVOX_ERR_EPS: return "accuracy out of range";
+        case HVOX_ERR_OOM: return "out of device memory";
+        case HVOX_ERR_HIP: return "HIP runtime error";
+        case HVOX_ERR_STATE: return "invalid plan state";
+        default: return "unknown error";
+    }
+}
+
+const char *hvox_last_error(void) { return g_last_error.c_str(); }
+
+int hvox_kernel_params(double eps, double sigma, int32_t *w, double *beta)
+{
+    if (!w || !beta) return fail(HVOX_ERR_ARG, "NULL output");
+    int wi = 0;
+    int rc = es_params(eps, sigma, &wi, beta);
+    if (rc) return fail(rc, "no kernel for this eps / sigma");
+    *w = wi;
+    return HVOX_OK;
+}
+
+int hvox_alg1(const double B[3], const double P[3], double v_max, double alpha, double h[3], double eta[3])
+{
+    if (!B || !P || !h || !eta) return fail(HVOX_ERR_ARG, "NULL argument");
+    int rc = alg1(B, P, v_max, alpha, h, eta);
+    if (rc) return fail(rc, "Algorithm 1: widths and budget must be positive, alpha >= 1");
+    return HVOX_OK;
+}
+
+int64_t hvox_partition(const double *x, int64_t n, const double h[3], int32_t *labels)
+{
+    if (!h) return fail(HVOX_ERR_ARG, "NULL h");
+    try {
+        int64_t r = partition(x, n, h, labels);
+        if (r < 0) return fail(static_cast<int>(r), "Algorithm 2: bad points or box dimensions");
+        return r;
+    } catch (const std::bad_alloc &) {
+        return fail(HVOX_ERR_OOM, "host allocation failed");
+    }
+}
+
+int hvox_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t n_pix, double eps, int32_t dtype,
+              const hvox_opts *opts, void *stream, hvox_plan_t *out)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!out) return fail(HVOX_ERR_ARG, "NULL output plan pointer");
+    *out = nullptr;
+    if (n_vis < 0 || n_pix < 0) return fail(HVOX_ERR_ARG, "negative point count");
+    if ((n_vis > 0 && !uvw) || (n_pix > 0 && !xyz)) return fail(HVOX_ERR_ARG, "NULL coordinates");
+    if (n_vis > INT32_MAX || n_pix > INT32_MAX) return fail(HVOX_ERR_ARG, "more than 2^31-1 points");
+    if (dtype != HVOX_F32 && dtype != HVOX_F64) return fail(HVOX_ERR_ARG, "dtype must be HVOX_F32 or HVOX_F64");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(HVOX_ERR_EPS, "eps must be finite and >= 0");
+    Params prm;
+    prm.dtype = dtype;
+    prm.eps = eps;
+    hvox_opts o{};
+    if (opts) o = *opts;
+    prm.sigma = o.upsampfac == 0.0 ? 1.25 : o.upsampfac;
+    if (!(prm.sigma >= 1.25 && prm.sigma <= 2.0)) return fail(HVOX_ERR_ARG, "upsampfac must lie in [1.25, 2]");
+    prm.alpha = o.anisotropy == 0.0 ? 1.0 : o.anisotropy;
+    if (!(prm.alpha >= 1.0) || !std::isfinite(prm.alpha)) return fail(HVOX_ERR_ARG, "anisotropy must be >= 1");
+    prm.max_fft_bytes = o.max_fft_bytes == 0.0 ? 500e6 : o.max_fft_bytes;
+    if (!(prm.max_fft_bytes > 0.0)) return fail(HVOX_ERR_ARG, "max_fft_bytes must be > 0");
+    prm.ws_cap = o.workspace_bytes == 0.0 ? 4.0 * 1024 * 1024 * 1024 : o.workspace_bytes;
+    if (!(prm.ws_cap > 0.0) || !std::isfinite(prm.ws_cap)) return fail(HVOX_ERR_ARG, "workspace_bytes must be > 0");
+    prm.direct_threshold = o.direct_threshold;
+    if (std::isnan(prm.direct_threshold)) return fail(HVOX_ERR_ARG, "direct_threshold is NaN");
+    prm.flags = o.flags;
+    prm.all_direct = eps == 0.0 || std::isinf(prm.direct_threshold);
+    if (eps > 0.0) {
+        const double floor_eps = dtype == HVOX_F64 ? 1e-10 : 1e-6;
+        if (eps < floor_eps) return fail(HVOX_ERR_EPS, "eps below the floor of this dtype");
+        int rc = es_params(std::min(eps, 0.5), prm.sigma, &prm.w, &prm.beta);
+        if (rc) return fail(rc, "no kernel for this eps");
+    } else {
+        prm.w = 3;
+        prm.beta = 1.0;
+    }
+    auto *pl = new (std::nothrow) hvox_plan_s();
+    if (!pl) return fail(HVOX_ERR_OOM, "host allocation failed");
+    pl->host_only = (prm.flags & HVOX_PLAN_HOST_ONLY) != 0;
+    std::string err;
+    int rc;
+    try {
+        rc = make_host_plan(uvw, n_vis, xyz, n_pix, prm, o.vis_chunk, o.sky_chunk, &pl->hp, &err);
+        if (rc == HVOX_OK && !pl->host_only) rc = build_device(pl, static_cast<hipStream_t>(stream), &err);
+    } catch (const std::bad_alloc &) {
+        rc = HVOX_ERR_OOM;
+        err = "host allocation failed";
+    } catch (const std::exception &ex) {
+        rc = HVOX_ERR_ARG;
+        err = ex.what();
+    }
+    if (rc != HVOX_OK) {
+        release(pl);
+        delete pl;
+        return fail(rc, err);
+    }
+    pl->last_stream = static_cast<hipStream_t>(stream);
+    pl->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = pl;
+    return HVOX_OK;
+}
+
+int hvox_synthesis(hvox_plan_t plan, const void *sky, void *vis, int32_t ntrans, void *stream)
+{
+    try {
+        return transform(plan, true, sky, vis, ntrans, stream);
+    } catch (...) {
+        return fail(HVOX_ERR_HIP, "unexpected failure in hvox_synthesis");
+    }
+}
+
+int hvox_analysis(hvox_plan_t plan, const void *vis, void *sky, int32_t ntrans, void *stream)
+{
+    try {
+        return transform(plan, false, vis, sky, ntrans, stream);
+    } catch (...) {
+        return fail(HVOX_ERR_HIP, "unexpected failure in hvox_analysis");
+    }
+}
+
+int hvox_free(hvox_plan_t plan)
+{
+    if (!plan) return HVOX_OK;
+    if (!plan->host_only && plan->last_stream) (void)hipStreamSynchronize(plan->last_stream);
+    release(plan);
+    delete plan;
+    return HVOX_OK;
+}
+
+int hvox_plan_info(hvox_plan_t plan, hvox_plan_info_t *out)
+{
+    if (!plan || !out) return fail(HVOX_ERR_ARG, "NULL argument");
+    const HostPlan &hp = plan->hp;
+    std::memset(out, 0, sizeof(*out));
+    out->n_vis = hp.n_vis;
+    out->n_pix = hp.n_pix;
+    out->dtype = hp.prm.dtype;
+    out->w = hp.prm.w;
+    out->beta = hp.prm.beta;
+    out->sigma = hp.prm.sigma;
+    out->eps = hp.prm.eps;
+    for (int d = 0; d < 3; ++d) { out->h[d] = hp.h[d]; out->eta[d] = hp.eta[d]; }
+    out->n_vis_chunks = hp.vis.nc;
+    out->n_sky_chunks = hp.sky.nc;
+    out->n_pairs_nufft = static_cast<int64_t>(hp.syn.pairs.size());
+    out->n_pairs_direct = static_cast<int64_t>(hp.vis.nc) * hp.sky.nc - out->n_pairs_nufft;
+    out->n_batches = static_cast<int64_t>(hp.syn.batches.size());
+    const int64_t delta = hp.prm.dtype == HVOX_F64 ? 16 : 8;
+    out->workspace_bytes = hp.ws_elems * delta;
+    out->max_pair_workspace_bytes = hp.max_pair_ws * delta;
+    if (plan->host_only) {
+        int64_t r = 16 * (hp.n_vis + hp.n_pix) + 4 * (hp.n_vis + hp.n_pix) + 8 * (hp.n_vis + hp.n_pix) +
+                    16 * std::max(hp.n_vis, hp.n_pix);
+        r += static_cast<int64_t>((hp.syn.pairs.size() + hp.ana.pairs.size()) * sizeof(PairDev));
+        r += static_cast<int64_t>((hp.syn.direct.size() + hp.ana.direct.size()) * sizeof(DirectItem));
+        out->resident_bytes = r;
+    } else {
+        out->resident_bytes = static_cast<int64_t>(plan->resident_bytes);
+    }
+    out->grid_cells = hp.syn.grid_cells;
+    out->direct_terms = hp.syn.direct_terms;
+    out->est_seconds = hp.syn.est_seconds + hp.ana.est_seconds;
+    out->plan_seconds = plan->plan_seconds;
+    return HVOX_OK;
+}
+
+int hvox_plan_permutation(hvox_plan_t plan, int32_t *vis_perm, int32_t *sky_perm)
+{
+    if (!plan) return fail(HVOX_ERR_ARG, "NULL plan");
+    if (vis_perm) std::memcpy(vis_perm, plan->hp.vis.perm.data(), sizeof(int32_t) * plan->hp.n_vis);
+    if (sky_perm) std::memcpy(sky_perm, plan->hp.sky.perm.data(), sizeof(int32_t) * plan->hp.n_pix);
+    return HVOX_OK;
+}
+
+int hvox_plan_chunks(hvox_plan_t plan, int32_t *vis_chunk, int32_t *sky_chunk)
+{
+    if (!plan) return fail(HVOX_ERR_ARG, "NULL plan");
+    if (vis_chunk) std::memcpy(vis_chunk, plan->hp.vis.label.data(), sizeof(int32_t) * plan->hp.n_vis);
+    if (sky_chunk) std::memcpy(sky_chunk, plan->hp.sky.label.data(), sizeof(int32_t) * plan->hp.n_pix);
+    return HVOX_OK;
+}
+
+int hvox_stats(hvox_plan_t plan, hvox_stats_t *out)
+{
+    if (!plan || !out) return fail(HVOX_ERR_ARG, "NULL argument");
+    if (!plan->host_only) {
+        hipError_t e = resolve_timing(plan);
+        if (e != hipSuccess) return fail(HVOX_ERR_HIP, std::string("HIP: ") + hipGetErrorString(e));
+    }
+    *out = plan->stats;
+    return HVOX_OK;
+}
+
+int hvox_stats_reset(hvox_plan_t plan)
+{
+    if (!plan) return fail(HVOX_ERR_ARG, "NULL plan");
+    if (!plan->host_only) {
+        hipError_t e = resolve_timing(plan);
+        if (e != hipSuccess) return fail(HVOX_ERR_HIP, std::string("HIP: ") + hipGetErrorString(e));
+    }
+    plan->stats = hvox_stats_t{};
+    return HVOX_OK;
+}
+
+}  // extern "C"
+
+// ---- kernel-level test entry point (include/hvox_testing.h) ---------------------
+#include "../../include/hvox_testing.h"
+
+extern "C" int hvox_test_fft(int32_t dtype, int32_t n, int32_t nin, int32_t nlines, int32_t wstart, int32_t wcount,
+                             int32_t sign, const void *in, void *out, void *stream)
+{
+    using namespace hvox;
+    if ((dtype != HVOX_F32 && dtype != HVOX_F64) || n < 2 || n > kFftMaxLen || (n & 1) || nin < 2 || (nin & 1) ||
+        nin > n || nlines < 1 || wcount < 1 || wcount > n || (sign != 1 && sign != -1) || !in || !out)
+        return fail(HVOX_ERR_ARG, "bad FFT test arguments");
+    if (smooth_even(n) != n) return fail(HVOX_ERR_ARG, "n must be 2-3-5 smooth");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t delta = dtype == HVOX_F64 ? 16 : 8;
+    // one sub-problem whose x pass is exactly this transform: grid 1 is
+    // [1][nlines][nin], pre-correction 1, output window along x only
+    PairDev pd{};
+    pd.n1[0] = nin; pd.n1[1] = nlines; pd.n1[2] = 1;
+    pd.n2[0] = n; pd.n2[1] = nlines; pd.n2[2] = 1;
+    pd.wstart[0] = wstart; pd.wcount[0] = wcount;
+    pd.wstart[1] = 0; pd.wcount[1] = nlines; pd.wstart[2] = 0; pd.wcount[2] = 1;
+    pd.nrad[0] = factor_radices(n, pd.radix[0]);
+    pd.lines_per_tile[0] = std::max(1, std::min(kFftMaxLines, kFftElems / n));
+    const int64_t lines = nlines;
+    const int64_t tiles = (lines + pd.lines_per_tile[0] - 1) / pd.lines_per_tile[0];
+    const int64_t gin = static_cast<int64_t>(nin) * nlines, gout = static_cast<int64_t>(wcount) * nlines;
+    pd.bufA = 0;
+    pd.bufB = gin;
+    pd.precor[0] = 0; pd.precor[1] = nin; pd.precor[2] = nin + nlines;
+    pd.tw[0] = 0;
+    std::vector<double> ones(nin + nlines + 1, 1.0);
+    std::vector<double2> tw64(n);
+    std::vector<float2> tw32(n);
+    for (int j = 0; j < n; ++j) {
+        double a = 2.0 * M_PI * j / n;
+        tw64[j] = make_double2(std::cos(a), -std::sin(a));
+        tw32[j] = make_float2(static_cast<float>(std::cos(a)), static_cast<float>(-std::sin(a)));
+    }
+    std::vector<int64_t> prefix = {0, tiles};
+    void *d_ws = nullptr, *d_tw = nullptr, *d_pd = nullptr, *d_pre = nullptr, *d_one = nullptr;
+    auto cleanup = [&]() {
+        for (void *p : {d_ws, d_tw, d_pd, d_pre, d_one}) if (p) (void)hipFree(p);
+    };
+    hipError_t e = hipMalloc(&d_ws, delta * (gin + gout));
+    if (e == hipSuccess) e = hipMalloc(&d_tw, delta * n);
+    if (e == hipSuccess) e = hipMalloc(&d_pd, sizeof(PairDev));
+    if (e == hipSuccess) e = hipMalloc(&d_pre, sizeof(int64_t) * 2);
+    if (e == hipSuccess) e = hipMalloc(&d_one, sizeof(double) * ones.size());
+    if (e == hipSuccess) e = hipMemcpyAsync(d_ws, in, delta * gin, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_tw, dtype == HVOX_F64 ? static_cast<const void *>(tw64.data()) : tw32.data(), delta * n,
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_pd, &pd, sizeof(PairDev), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_pre, prefix.data(), sizeof(int64_t) * 2, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_one, ones.data(), sizeof(double) * ones.size(), hipMemcpyHostToDevice, st);
+    const int lds = pd.lines_per_tile[0] * n;
+    if (e == hipSuccess)
+        e = dtype == HVOX_F64
+                ? launch_fft<double>(static_cast<PairDev *>(d_pd), static_cast<int64_t *>(d_pre), 1, tiles, 0, d_ws,
+                                     d_tw, static_cast<double *>(d_one), lds, sign, st)
+                : launch_fft<float>(static_cast<PairDev *>(d_pd), static_cast<int64_t *>(d_pre), 1, tiles, 0, d_ws,
+                                    d_tw, static_cast<double *>(d_one), lds, sign, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, static_cast<char *>(d_ws) + delta * gin, delta * gout, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    cleanup();
+    if (e != hipSuccess) return fail(HVOX_ERR_HIP, std::string("HIP: ") + hipGetErrorString(e));
+    return HVOX_OK;
+}

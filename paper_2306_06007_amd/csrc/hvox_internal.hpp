@@ -1,0 +1,137 @@
+// Internal definitions shared by the host planner, the executor and the HIP
+// kernels of the HVOX library.  Not part of the public ABI (include/hvox.h).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hvox.h"
+
+namespace hvox {
+
+// ---- compile-time limits -------------------------------------------------
+constexpr int kWMax = 24;            // largest kernel support handled by the kernels
+constexpr int kFftThreads = 256;     // threads of one FFT workgroup
+constexpr int kFftElems = 4096;      // complex elements (lines x length) held in LDS by one workgroup
+constexpr int kFftMaxLen = 4096;     // longest 1D FFT (one line must fit a workgroup)
+constexpr int kFftMaxLines = 64;     // lines per FFT workgroup
+constexpr int kDirectTile = 256;     // targets per direct-sum workgroup (one per thread)
+constexpr int kDirectSeg = 2048;     // sources per direct-sum work item
+constexpr int kWavesPerBlock = 4;    // spread / interp: one wavefront per point
+constexpr int kMaxStages = 16;       // radix stages per FFT length
+
+// ---- one type-3 sub-problem (source chunk -> target chunk) on the device ---
+// Sub-problem math (Sect. 3, the four type-3 steps; centring as in the
+// published type-3 method the paper builds on):
+//   f_k = e^{2 pi i iota s_k.x_c} sum_n [c_n e^{2 pi i iota s_c.x'_n}] e^{2 pi i iota s'_k.x'_n}
+// with x' = x - x_c, s' = s - s_c.  Sources spread on grid 1 at
+// t = x' * kscale (kscale = 2 sigma S, S = target half-width), grid 1 is
+// pre-corrected and FFT'd on the upsampled grid 2, targets interpolate at
+// tau = s' * tscale (tscale = n2 / (2 sigma S)) and are deconvolved.
+struct PairDev {
+    int64_t src_off, src_cnt;    // chunk-order range of the sources
+    int64_t tgt_off, tgt_cnt;    // chunk-order range of the targets
+    double xc[3];                // source chunk centre
+    double sc[3];                // target chunk centre
+    double kscale[3];            // grid-1 coordinate scale of the sources
+    double tscale[3];            // grid-2 coordinate scale of the targets
+    int32_t n1[3];               // grid-1 size (modes -n1/2 .. n1/2-1)
+    int32_t n2[3];               // grid-2 (FFT) size
+    int32_t wstart[3];           // first kept FFT output index (may be negative: periodic)
+    int32_t wcount[3];           // kept FFT outputs per dimension
+    int32_t nrad[3];             // radix stages per dimension
+    int32_t lines_per_tile[3];   // FFT lines per workgroup, per pass
+    int64_t bufA, bufB;          // complex-element offsets of the two grid buffers in the workspace
+    int64_t precor[3];           // offsets into the pre-correction table (n1[d] entries each)
+    int64_t tw[3];               // offsets into the twiddle table (n2[d] entries each)
+    uint8_t radix[3][kMaxStages];
+};
+
+// ---- direct-sum work item: <= kDirectTile targets x <= kDirectSeg sources --
+struct DirectItem {
+    int64_t tgt_off;             // chunk-order index of the first target
+    int64_t src_off;             // chunk-order index of the first source
+    int32_t tgt_cnt;
+    int32_t src_cnt;
+};
+
+// ---- host-side plan pieces -------------------------------------------------
+struct ChunkSet {
+    int64_t n = 0;
+    int32_t nc = 0;
+    std::vector<int32_t> label;      // [n] chunk id of each user-order point
+    std::vector<int32_t> perm;       // [n] user index of each chunk-order point
+    std::vector<int64_t> off;        // [nc + 1] chunk start in chunk order
+    std::vector<double> lo, hi;      // [nc * 3] tight boxes
+    std::vector<double> ctr, half;   // [nc * 3] centres and half-widths
+};
+
+struct Batch {
+    int64_t pair0 = 0, npairs = 0;       // range in the direction's PairDev array
+    int64_t pts = 0, tgts = 0;           // spread points, interp targets
+    int64_t tiles[3] = {0, 0, 0};        // FFT workgroups per pass
+    int64_t zero_off = 0, zero_cnt = 0;  // workspace range (complex elements) to clear before spreading
+    int64_t ws_end = 0;                  // end of the batch's workspace use (complex elements)
+    int64_t pre_pts = 0, pre_tgts = 0;   // offsets into the prefix arrays
+    int64_t pre_tiles[3] = {0, 0, 0};
+    int32_t lds_elems[3] = {0, 0, 0};    // largest LDS need per pass (complex elements)
+    int32_t max_pass_len[3] = {0, 0, 0};
+};
+
+struct DirPlan {                         // one direction (synthesis or analysis)
+    std::vector<PairDev> pairs;          // NUFFT sub-problems, batch-contiguous
+    std::vector<Batch> batches;
+    std::vector<int64_t> pre_pts, pre_tgts, pre_tiles[3];   // per batch: npairs+1 prefix sums
+    std::vector<DirectItem> direct;
+    double grid_cells = 0.0, direct_terms = 0.0;
+    double est_seconds = 0.0;
+    double alg_bytes[HVOX_K_COUNT] = {0};
+    double alg_flops[HVOX_K_COUNT] = {0};
+};
+
+struct Params {
+    int dtype = HVOX_F32;
+    double eps = 1e-4;
+    double sigma = 1.25;
+    int w = 8;
+    double beta = 0.0;
+    bool all_direct = false;
+    double direct_threshold = -1.0;
+    double max_fft_bytes = 500e6;
+    double alpha = 1.0;
+    double ws_cap = 4.0 * 1024 * 1024 * 1024;
+    int flags = 0;
+};
+
+struct HostPlan {
+    Params prm;
+    int64_t n_vis = 0, n_pix = 0;
+    std::vector<double> uvw, xyz;        // user order, [n][3]
+    ChunkSet vis, sky;
+    double h[3] = {0, 0, 0}, eta[3] = {0, 0, 0};
+    DirPlan syn, ana;                    // syn: sky -> vis (iota = -1); ana: vis -> sky (iota = +1)
+    int64_t ws_elems = 0;                // workspace size (complex elements)
+    int64_t max_pair_ws = 0;
+    // unique FFT-length tables: (n1, n2) pre-correction tables and n2 twiddles
+    std::vector<double> precor_nu;       // nu = l / n2 of every pre-correction entry
+    std::vector<int32_t> tw_len;         // lengths with a twiddle table
+    std::vector<int64_t> tw_off;         // offsets (complex elements) of each table
+    int64_t tw_total = 0;
+    // deconvolution: per chunk S_eff (target scale) for each direction
+    std::vector<double> syn_tgt_scale;   // [n_vis_chunks * 3]: 1 / (2 sigma S_eff) for vis targets
+    std::vector<double> ana_tgt_scale;   // [n_sky_chunks * 3]
+};
+
+// ---- planner entry points (planner.cpp, host only) ------------------------
+int es_params(double eps, double sigma, int *w, double *beta);
+int alg1(const double B[3], const double P[3], double v_max, double alpha, double h[3], double eta[3]);
+int64_t partition(const double *x, int64_t n, const double h[3], int32_t *labels);
+int make_host_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t n_pix,
+                   const Params &prm, const int32_t *vis_chunk, const int32_t *sky_chunk,
+                   HostPlan *hp, std::string *err);
+int32_t smooth_even(int64_t n);
+int factor_radices(int32_t n, uint8_t *radix);
+void gauss_legendre(int n, std::vector<double> *x, std::vector<double> *w);
+
+}  // namespace hvox

@@ -1,0 +1,624 @@
+// HIP kernels of the HVOX library for gfx950 (MI355X): the hot path of the
+// chunked 3D type-3 NUFFT (HVOX Sect. 3 and 3.1) and of its block-level
+// direct evaluation.
+//
+// Data layout in HBM
+//  * coordinates: float64 structure-of-arrays [3][n] in chunk order;
+//  * user data:   complex (float2 / double2) in user order, gathered through
+//                 the chunk-order permutation (Sect. 4, chunk-order views);
+//  * grids:       per sub-problem two buffers in one workspace.  Grid 1 is
+//                 [n1z][n1y][n1x]; every FFT pass reads contiguous lines and
+//                 writes its kept outputs transposed, rotating the axes
+//                 (x-pass -> [wx][n1z][n1y], y-pass -> [wy][wx][n1z],
+//                 z-pass -> [wz][wy][wx]) so the next pass reads contiguous
+//                 lines again and the interpolation reads an x-fastest grid;
+//  * accumulator: float64 complex per target (chunk order).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hvox_internal.hpp"
+
+namespace hvox {
+
+template <typename T> struct C2;
+template <> struct C2<float> { using type = float2; };
+template <> struct C2<double> { using type = double2; };
+template <typename T> using cplx = typename C2<T>::type;
+
+template <typename T> __device__ __forceinline__ cplx<T> mk(T a, T b) { cplx<T> r; r.x = a; r.y = b; return r; }
+template <typename T> __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b)
+{
+    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T> __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+// multiply by s*i (s = +1 or -1)
+template <typename T> __device__ __forceinline__ cplx<T> cmuli(cplx<T> a, T s) { return mk<T>(-s * a.y, s * a.x); }
+
+// exponential of semicircle ES(z) = exp(beta (sqrt(1 - z^2) - 1)), |z| < 1
+__device__ __forceinline__ float es_kernel(float z, float beta)
+{
+    float q = 1.0f - z * z;
+    return q > 0.0f ? __expf(beta * (sqrtf(q) - 1.0f)) : 0.0f;
+}
+__device__ __forceinline__ double es_kernel(double z, double beta)
+{
+    double q = 1.0 - z * z;
+    return q > 0.0 ? exp(beta * (sqrt(q) - 1.0)) : 0.0;
+}
+
+// exp(2 pi i s f) for a phase f in cycles, evaluated in float64 after
+// reduction to [-1/2, 1/2]
+__device__ __forceinline__ double2 cis_cycles(double f, double s)
+{
+    double r = f - rint(f);
+    double sn, cs;
+    sincospi(2.0 * r, &sn, &cs);
+    return make_double2(cs, s * sn);
+}
+
+__device__ __forceinline__ int64_t find_segment(const int64_t *__restrict__ prefix, int n, int64_t g)
+{
+    int lo = 0, hi = n - 1;          // largest p with prefix[p] <= g
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// fills
+// ---------------------------------------------------------------------------
+__global__ void k_zero(double *__restrict__ p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// deconvolution factors 1 / prod_d Psi_hat(nu_d) of every target, where
+// nu_d = (s_d - s_c,d) h_d and Psi_hat(nu) = (w/2) int_{-1}^{1} ES(z) cos(pi nu w z) dz
+// (Gauss-Legendre; aq = weight * ES(node)).
+// ---------------------------------------------------------------------------
+__global__ void k_deconv(const double *__restrict__ xyz, int64_t n, const int32_t *__restrict__ chunk_of,
+                         const double *__restrict__ ctr, const double *__restrict__ hscale,
+                         const double *__restrict__ zq, const double *__restrict__ aq, int nq, int w,
+                         double *__restrict__ out)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int32_t c = chunk_of[k];
+    double prod = 1.0;
+    for (int d = 0; d < 3; ++d) {
+        double nu = (xyz[d * n + k] - ctr[3 * c + d]) * hscale[3 * c + d];
+        double s = 0.0;
+        for (int q = 0; q < nq; ++q) s += aq[q] * cospi(nu * w * zq[q]);
+        prod *= 0.5 * w * s;
+    }
+    out[k] = 1.0 / prod;
+}
+
+// ---------------------------------------------------------------------------
+// spreading (type-3 step 1, "spreading ... followed by tapering" of Sect. 3):
+//   b_l += c'_n prod_d ES((l_d - t_nd) 2/w),  c'_n = c_n exp(2 pi i iota s_c.x'_n)
+// One wavefront per source point; the lanes cover the w x w (x, y) rows of
+// its footprint and loop over z, adding with float atomics (the footprints
+// of neighbouring points are disjoint in the sparse regime this path serves,
+// so each row is a short contiguous run of one cache line or two).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pairs, const int64_t *__restrict__ prefix,
+                                                int npairs, int64_t total, const double *__restrict__ xyz, int64_t nsrc,
+                                                const int32_t *__restrict__ perm, const cplx<T> *__restrict__ in,
+                                                cplx<T> *__restrict__ ws, int w, T beta, double iota)
+{
+    __shared__ T ker[kWavesPerBlock][3 * kWMax];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const T two_over_w = T(2) / T(w);
+    for (int64_t base = (int64_t)blockIdx.x * kWavesPerBlock; base < total;
+         base += (int64_t)gridDim.x * kWavesPerBlock) {
+        const int64_t g = base + wv;
+        const bool active = g < total;
+        int p = 0;
+        int l0[3] = {0, 0, 0};
+        cplx<T> cval = mk<T>(T(0), T(0));
+        if (active) {
+            p = (int)find_segment(prefix, npairs, g);
+            const PairDev &P = pairs[p];
+            const int64_t n = P.src_off + (g - prefix[p]);
+            double xp[3], t[3];
+            double ph = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                xp[d] = xyz[d * nsrc + n] - P.xc[d];
+                t[d] = xp[d] * P.kscale[d];
+                ph += P.sc[d] * xp[d];
+            }
+            double2 e = cis_cycles(ph, iota);
+            cplx<T> c = in[perm[n]];
+            cval = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
+            for (int d = 0; d < 3; ++d) l0[d] = (int)ceil(t[d] - 0.5 * w);
+            if (lane < 3 * w) {
+                int d = lane / w, q = lane - d * w;
+                T off = T((double)(l0[d] + q) - t[d]);
+                ker[wv][lane] = es_kernel(off * two_over_w, beta);
+            }
+        }
+        __syncthreads();
+        if (active) {
+            const PairDev &P = pairs[p];
+            const int n1x = P.n1[0], n1y = P.n1[1], n1z = P.n1[2];
+            const int ix0 = l0[0] + n1x / 2, iy0 = l0[1] + n1y / 2, iz0 = l0[2] + n1z / 2;
+            T *grid = reinterpret_cast<T *>(ws + P.bufA);
+            for (int e = lane; e < w * w; e += 64) {
+                const int dy = e / w, dx = e - dy * w;
+                const int ix = ix0 + dx, iy = iy0 + dy;
+                if (ix < 0 || ix >= n1x || iy < 0 || iy >= n1y) continue;
+                const T kxy = ker[wv][dx] * ker[wv][w + dy];
+                const cplx<T> v = cscale<T>(cval, kxy);
+                for (int dz = 0; dz < w; ++dz) {
+                    const int iz = iz0 + dz;
+                    if (iz < 0 || iz >= n1z) continue;
+                    const T kz = ker[wv][2 * w + dz];
+                    const int64_t idx = ((int64_t)iz * n1y + iy) * n1x + ix;
+                    atomicAdd(grid + 2 * idx, v.x * kz);
+                    atomicAdd(grid + 2 * idx + 1, v.y * kz);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FFT passes (type-3 step 2: pre-correction + zero-padded FFT on grid 2).
+// ---------------------------------------------------------------------------
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(cplx<T> *u, T s)
+{
+    if constexpr (R == 2) {
+        cplx<T> a = u[0], b = u[1];
+        u[0] = cadd<T>(a, b);
+        u[1] = csub<T>(a, b);
+    } else if constexpr (R == 3) {
+        const T h = T(0.86602540378443864676);
+        cplx<T> t1 = cadd<T>(u[1], u[2]), t2 = csub<T>(u[1], u[2]);
+        cplx<T> m = mk<T>(u[0].x - T(0.5) * t1.x, u[0].y - T(0.5) * t1.y);
+        cplx<T> r = cmuli<T>(cscale<T>(t2, h), s);
+        u[0] = cadd<T>(u[0], t1);
+        u[1] = cadd<T>(m, r);
+        u[2] = csub<T>(m, r);
+    } else if constexpr (R == 4) {
+        cplx<T> a = cadd<T>(u[0], u[2]), b = csub<T>(u[0], u[2]);
+        cplx<T> c = cadd<T>(u[1], u[3]), d = csub<T>(u[1], u[3]);
+        cplx<T> id = cmuli<T>(d, s);
+        u[0] = cadd<T>(a, c);
+        u[2] = csub<T>(a, c);
+        u[1] = cadd<T>(b, id);
+        u[3] = csub<T>(b, id);
+    } else {   // R == 5
+        const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
+        const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);
+        cplx<T> t1 = cadd<T>(u[1], u[4]), t2 = cadd<T>(u[2], u[3]);
+        cplx<T> t3 = csub<T>(u[1], u[4]), t4 = csub<T>(u[2], u[3]);
+        cplx<T> a1 = mk<T>(u[0].x + c1 * t1.x + c2 * t2.x, u[0].y + c1 * t1.y + c2 * t2.y);
+        cplx<T> a2 = mk<T>(u[0].x + c2 * t1.x + c1 * t2.x, u[0].y + c2 * t1.y + c1 * t2.y);
+        cplx<T> b1 = cmuli<T>(mk<T>(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y), s);
+        cplx<T> b2 = cmuli<T>(mk<T>(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y), s);
+        u[0] = cadd<T>(u[0], cadd<T>(t1, t2));
+        u[1] = cadd<T>(a1, b1);
+        u[4] = csub<T>(a1, b1);
+        u[2] = cadd<T>(a2, b2);
+        u[3] = csub<T>(a2, b2);
+    }
+}
+
+// One Stockham stage of radix R on nl lines of length n held in LDS, in
+// place: every thread first reads and transforms its butterflies into
+// registers, then (after a barrier) writes them back in autosorted order.
+// Butterfly i of a line: k = i mod p, inputs x[i + q n/R] twiddled by
+// w^(k q n / (p R)), outputs at (i - k) R + k + m p.
+template <typename T, int R>
+__device__ void fft_stage(cplx<T> *lds, int nl, int n, int p, const cplx<T> *__restrict__ tw, T s)
+{
+    constexpr int MAXB = (kFftElems / R + kFftThreads - 1) / kFftThreads;
+    const int nbf = n / R;
+    const int total = nl * nbf;
+    const int twstep = n / (p * R);
+    cplx<T> v[MAXB][R];
+#pragma unroll
+    for (int c = 0; c < MAXB; ++c) {
+        const int b = threadIdx.x + c * kFftThreads;
+        if (b < total) {
+            const int j = b / nbf, i = b - j * nbf;
+            const int k = i % p;
+            const cplx<T> *line = lds + j * n;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                cplx<T> u = line[i + q * nbf];
+                if (q > 0) {
+                    cplx<T> t = tw[k * q * twstep];
+                    t.y *= -s;   // table holds exp(-2 pi i j/n); sign s = -1 keeps it, +1 conjugates
+                    u = cmul<T>(u, t);
+                }
+                v[c][q] = u;
+            }
+            dft_small<T, R>(v[c], s);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < MAXB; ++c) {
+        const int b = threadIdx.x + c * kFftThreads;
+        if (b < total) {
+            const int j = b / nbf, i = b - j * nbf;
+            const int k = i % p;
+            cplx<T> *line = lds + j * n;
+            const int o = (i - k) * R + k;
+#pragma unroll
+            for (int m = 0; m < R; ++m) line[o + m * p] = v[c][m];
+        }
+    }
+    __syncthreads();
+}
+
+// One axis pass for every sub-problem of a batch.  Lines of the pass input
+// are contiguous ([lines][nin]); element e of a line is mode l = e - nin/2,
+// placed at FFT slot l mod n (zero elsewhere: the zero padding of grid 1 into
+// grid 2 is never stored).  The x pass also applies the separable
+// pre-correction 1/Phi_hat(l/n2) of all three axes.  Output q of the kept
+// window is FFT index (wstart + q) mod n, written to out[q][line].
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restrict__ pairs,
+                                                          const int64_t *__restrict__ prefix, int npairs, int pass,
+                                                          cplx<T> *__restrict__ ws, const cplx<T> *__restrict__ twtab,
+                                                          const double *__restrict__ precor, T s)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T> *lds = reinterpret_cast<cplx<T> *>(smem_raw);
+    const int p = (int)find_segment(prefix, npairs, blockIdx.x);
+    const PairDev &P = pairs[p];
+    const int64_t tile = (int64_t)blockIdx.x - prefix[p];
+    const int n = P.n2[pass], nin = P.n1[pass];
+    const int wst = P.wstart[pass], wcnt = P.wcount[pass];
+    int64_t lines;
+    const cplx<T> *src;
+    cplx<T> *dst;
+    if (pass == 0) { lines = (int64_t)P.n1[2] * P.n1[1]; src = ws + P.bufA; dst = ws + P.bufB; }
+    else if (pass == 1) { lines = (int64_t)P.wcount[0] * P.n1[2]; src = ws + P.bufB; dst = ws + P.bufA; }
+    else { lines = (int64_t)P.wcount[1] * P.wcount[0]; src = ws + P.bufA; dst = ws + P.bufB; }
+    const int L = P.lines_per_tile[pass];
+    const int64_t line0 = tile * L;
+    const int nl = (int)min((int64_t)L, lines - line0);
+    const int half_in = nin / 2;
+
+    for (int e = threadIdx.x; e < nl * n; e += kFftThreads) {
+        const int j = e / n, f = e - j * n;
+        const int l = f < n / 2 ? f : f - n;
+        cplx<T> v = mk<T>(T(0), T(0));
+        if (l >= -half_in && l < half_in) {
+            const int64_t li = line0 + j;
+            v = src[li * nin + (l + half_in)];
+            if (pass == 0) {
+                const int64_t lz = li / P.n1[1], ly = li - lz * P.n1[1];
+                const double fac = precor[P.precor[0] + l + half_in] * precor[P.precor[1] + ly] *
+                                   precor[P.precor[2] + lz];
+                v = cscale<T>(v, T(fac));
+            }
+        }
+        lds[j * n + f] = v;
+    }
+    __syncthreads();
+    const cplx<T> *tw = twtab + P.tw[pass];
+    int pc = 1;
+    for (int st = 0; st < P.nrad[pass]; ++st) {
+        const int R = P.radix[pass][st];
+        if (R == 4) fft_stage<T, 4>(lds, nl, n, pc, tw, s);
+        else if (R == 2) fft_stage<T, 2>(lds, nl, n, pc, tw, s);
+        else if (R == 3) fft_stage<T, 3>(lds, nl, n, pc, tw, s);
+        else fft_stage<T, 5>(lds, nl, n, pc, tw, s);
+        pc *= R;
+    }
+    for (int e = threadIdx.x; e < nl * wcnt; e += kFftThreads) {
+        const int q = e / nl, j = e - q * nl;
+        int m = (wst + q) % n;
+        if (m < 0) m += n;
+        dst[(int64_t)q * lines + line0 + j] = lds[j * n + m];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// interpolation + deconvolution + post-phase (type-3 steps 3-4):
+//   f_k += exp(2 pi i iota s_k.x_c) / prod Psi_hat(.) * sum_m G_m prod_d ES((m_d - tau_kd) 2/w)
+// One wavefront per target; lanes cover the (x, y) rows of its w^3 window,
+// loop over z, and reduce across the wavefront.  Accumulation is float64
+// (cross-sub-problem sums stay in double precision).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pairs, const int64_t *__restrict__ prefix,
+                                                int npairs, int64_t total, const double *__restrict__ xyz, int64_t ntgt,
+                                                const double *__restrict__ deconv, const cplx<T> *__restrict__ ws,
+                                                double *__restrict__ acc, int w, T beta, double iota)
+{
+    __shared__ T ker[kWavesPerBlock][3 * kWMax];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const T two_over_w = T(2) / T(w);
+    for (int64_t base = (int64_t)blockIdx.x * kWavesPerBlock; base < total;
+         base += (int64_t)gridDim.x * kWavesPerBlock) {
+        const int64_t g = base + wv;
+        const bool active = g < total;
+        int p = 0;
+        int64_t k = 0;
+        int m0[3] = {0, 0, 0};
+        if (active) {
+            p = (int)find_segment(prefix, npairs, g);
+            const PairDev &P = pairs[p];
+            k = P.tgt_off + (g - prefix[p]);
+            double tau[3];
+            for (int d = 0; d < 3; ++d) {
+                tau[d] = (xyz[d * ntgt + k] - P.sc[d]) * P.tscale[d];
+                m0[d] = (int)ceil(tau[d] - 0.5 * w);
+            }
+            if (lane < 3 * w) {
+                int d = lane / w, q = lane - d * w;
+                T off = T((double)(m0[d] + q) - tau[d]);
+                ker[wv][lane] = es_kernel(off * two_over_w, beta);
+            }
+        }
+        __syncthreads();
+        T ar = T(0), ai = T(0);
+        if (active) {
+            const PairDev &P = pairs[p];
+            const int wx = P.wcount[0], wy = P.wcount[1], wz = P.wcount[2];
+            const int n2x = P.n2[0], n2y = P.n2[1], n2z = P.n2[2];
+            const int sx = P.wstart[0], sy = P.wstart[1], sz = P.wstart[2];
+            const cplx<T> *grid = ws + P.bufB;
+            for (int e = lane; e < w * w; e += 64) {
+                const int dy = e / w, dx = e - dy * w;
+                int qx = m0[0] + dx - sx, qy = m0[1] + dy - sy;
+                if (wx == n2x) { qx %= n2x; if (qx < 0) qx += n2x; }
+                if (wy == n2y) { qy %= n2y; if (qy < 0) qy += n2y; }
+                if (qx < 0 || qx >= wx || qy < 0 || qy >= wy) continue;
+                const T kxy = ker[wv][dx] * ker[wv][w + dy];
+                T sr = T(0), si = T(0);
+                for (int dz = 0; dz < w; ++dz) {
+                    int qz = m0[2] + dz - sz;
+                    if (wz == n2z) { qz %= n2z; if (qz < 0) qz += n2z; }
+                    if (qz < 0 || qz >= wz) continue;
+                    const T kz = ker[wv][2 * w + dz];
+                    const cplx<T> gv = grid[((int64_t)qz * wy + qy) * wx + qx];
+                    sr += gv.x * kz;
+                    si += gv.y * kz;
+                }
+                ar += sr * kxy;
+                ai += si * kxy;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            ar += __shfl_xor(ar, off, 64);
+            ai += __shfl_xor(ai, off, 64);
+        }
+        if (active && lane == 0) {
+            const PairDev &P = pairs[p];
+            double ph = 0.0;
+            for (int d = 0; d < 3; ++d) ph += xyz[d * ntgt + k] * P.xc[d];
+            const double2 e = cis_cycles(ph, iota);
+            const double dk = deconv[k];
+            const double vr = (double)ar * dk, vi = (double)ai * dk;
+            atomicAdd(acc + 2 * k, vr * e.x - vi * e.y);
+            atomicAdd(acc + 2 * k + 1, vr * e.y + vi * e.x);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// direct evaluation of a sub-problem block (Sect. 3.1, last bullet; the
+// eps = 0 mode of Sect. 4):  f_k += sum_n c_n exp(2 pi i iota s_k.x_n).
+// A workgroup owns <= 256 targets (one per thread) and <= kDirectSeg
+// sources, staged 256 at a time in LDS.  Per source tile with reference
+// point x_S and target-tile reference s_T,
+//   s_k.x_n = s_k.x_S + s_T.(x_n - x_S) + (s_k - s_T).(x_n - x_S):
+// the first two terms are evaluated once per (target, tile) and
+// (source, tile) in float64; only the small third term is evaluated per
+// (target, source) pair, in the plan's precision.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cis_rev_f32(float t, float &c, float &s)
+{
+    float r = t - rintf(t);
+    s = __builtin_amdgcn_sinf(r);
+    c = __builtin_amdgcn_cosf(r);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kDirectTile) void k_direct(const DirectItem *__restrict__ items,
+                                                        const double *__restrict__ sxyz, int64_t nsrc,
+                                                        const double *__restrict__ txyz, int64_t ntgt,
+                                                        const int32_t *__restrict__ perm,
+                                                        const cplx<T> *__restrict__ in, double *__restrict__ acc,
+                                                        double iota)
+{
+    __shared__ T lx[kDirectTile], ly[kDirectTile], lz[kDirectTile];
+    __shared__ cplx<T> lc[kDirectTile];
+    const DirectItem it = items[blockIdx.x];
+    const int tid = threadIdx.x;
+    const bool has_t = tid < it.tgt_cnt;
+    const int64_t k = it.tgt_off + (has_t ? tid : 0);
+    double sT[3], sk[3];
+    T sp[3];
+    for (int d = 0; d < 3; ++d) {
+        sT[d] = txyz[d * ntgt + it.tgt_off];
+        sk[d] = txyz[d * ntgt + k];
+        sp[d] = T(sk[d] - sT[d]);
+    }
+    const T sg = T(iota);
+    double accr = 0.0, acci = 0.0;
+    for (int s0 = 0; s0 < it.src_cnt; s0 += kDirectTile) {
+        const int64_t nS = it.src_off + s0;
+        double xS[3];
+        for (int d = 0; d < 3; ++d) xS[d] = sxyz[d * nsrc + nS];
+        const int cnt = min(kDirectTile, it.src_cnt - s0);
+        __syncthreads();
+        if (tid < cnt) {
+            const int64_t n = nS + tid;
+            double dxv[3];
+            double ph = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                dxv[d] = sxyz[d * nsrc + n] - xS[d];
+                ph += sT[d] * dxv[d];
+            }
+            lx[tid] = T(dxv[0]);
+            ly[tid] = T(dxv[1]);
+            lz[tid] = T(dxv[2]);
+            const double2 e = cis_cycles(ph, iota);
+            const cplx<T> c = in[perm[n]];
+            lc[tid] = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
+        }
+        __syncthreads();
+        T ar = T(0), ai = T(0);
+        for (int j = 0; j < cnt; ++j) {
+            const T t = sp[0] * lx[j] + sp[1] * ly[j] + sp[2] * lz[j];
+            T cs, sn;
+            if constexpr (sizeof(T) == 4) {
+                cis_rev_f32(t, cs, sn);
+            } else {
+                const T r = t - rint(t);
+                sincospi(T(2) * r, &sn, &cs);
+            }
+            sn *= sg;
+            const cplx<T> c = lc[j];
+            ar += c.x * cs - c.y * sn;
+            ai += c.x * sn + c.y * cs;
+        }
+        double ph = 0.0;
+        for (int d = 0; d < 3; ++d) ph += sk[d] * xS[d];
+        const double2 e = cis_cycles(ph, iota);
+        accr += (double)ar * e.x - (double)ai * e.y;
+        acci += (double)ar * e.y + (double)ai * e.x;
+    }
+    if (has_t) {
+        atomicAdd(acc + 2 * k, accr);
+        atomicAdd(acc + 2 * k + 1, acci);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// epilogue: cast the float64 accumulator to the plan's precision and scatter
+// to user order (the inverse of the chunk-order gather, Sect. 4 Fig. 5).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_finalize(const double *__restrict__ acc, int64_t n, const int32_t *__restrict__ perm,
+                           cplx<T> *__restrict__ out, int real_only)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    out[perm[k]] = mk<T>(T(acc[2 * k]), real_only ? T(0) : T(acc[2 * k + 1]));
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers (host)
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(int64_t n, int per, int64_t cap)
+{
+    int64_t b = (n + per - 1) / per;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return static_cast<unsigned>(b);
+}
+
+hipError_t launch_zero(double *p, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for(n, 256 * 8, 65536)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_deconv(const double *xyz, int64_t n, const int32_t *chunk_of, const double *ctr,
+                         const double *hscale, const double *zq, const double *aq, int nq, int w, double *out,
+                         hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_deconv, dim3(blocks_for(n, 256, INT32_MAX)), dim3(256), 0, st, xyz, n, chunk_of, ctr,
+                       hscale, zq, aq, nq, w, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spread(const PairDev *pairs, const int64_t *prefix, int npairs, int64_t total, const double *xyz,
+                         int64_t nsrc, const int32_t *perm, const void *in, void *ws, int w, double beta, double iota,
+                         hipStream_t st)
+{
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spread<T>, dim3(blocks_for(total, kWavesPerBlock, 1 << 16)), dim3(256), 0, st, pairs,
+                       prefix, npairs, total, xyz, nsrc, perm, static_cast<const cplx<T> *>(in),
+                       static_cast<cplx<T> *>(ws), w, T(beta), iota);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft(const PairDev *pairs, const int64_t *prefix, int npairs, int64_t tiles, int pass, void *ws,
+                      const void *tw, const double *precor, int lds_elems, double sign, hipStream_t st)
+{
+    if (tiles <= 0) return hipSuccess;
+    size_t lds = static_cast<size_t>(lds_elems) * sizeof(cplx<T>);
+    hipLaunchKernelGGL(k_fft_pass<T>, dim3(static_cast<unsigned>(tiles)), dim3(kFftThreads), lds, st, pairs, prefix,
+                       npairs, pass, static_cast<cplx<T> *>(ws), static_cast<const cplx<T> *>(tw), precor, T(sign));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_interp(const PairDev *pairs, const int64_t *prefix, int npairs, int64_t total, const double *xyz,
+                         int64_t ntgt, const double *deconv, const void *ws, double *acc, int w, double beta,
+                         double iota, hipStream_t st)
+{
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_interp<T>, dim3(blocks_for(total, kWavesPerBlock, 1 << 16)), dim3(256), 0, st, pairs,
+                       prefix, npairs, total, xyz, ntgt, deconv, static_cast<const cplx<T> *>(ws), acc, w, T(beta),
+                       iota);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_direct(const DirectItem *items, int64_t nitems, const double *sxyz, int64_t nsrc,
+                         const double *txyz, int64_t ntgt, const int32_t *perm, const void *in, double *acc,
+                         double iota, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_direct<T>, dim3(static_cast<unsigned>(nitems)), dim3(kDirectTile), 0, st, items, sxyz,
+                       nsrc, txyz, ntgt, perm, static_cast<const cplx<T> *>(in), acc, iota);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_finalize(const double *acc, int64_t n, const int32_t *perm, void *out, int real_only,
+                           hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize<T>, dim3(blocks_for(n, 256, INT32_MAX)), dim3(256), 0, st, acc, n, perm,
+                       static_cast<cplx<T> *>(out), real_only);
+    return hipGetLastError();
+}
+
+template hipError_t launch_spread<float>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
+                                         const int32_t *, const void *, void *, int, double, double, hipStream_t);
+template hipError_t launch_spread<double>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
+                                          const int32_t *, const void *, void *, int, double, double, hipStream_t);
+template hipError_t launch_fft<float>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,
+                                      const double *, int, double, hipStream_t);
+template hipError_t launch_fft<double>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,
+                                       const double *, int, double, hipStream_t);
+template hipError_t launch_interp<float>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
+                                         const double *, const void *, double *, int, double, double, hipStream_t);
+template hipError_t launch_interp<double>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
+                                          const double *, const void *, double *, int, double, double, hipStream_t);
+template hipError_t launch_direct<float>(const DirectItem *, int64_t, const double *, int64_t, const double *,
+                                         int64_t, const int32_t *, const void *, double *, double, hipStream_t);
+template hipError_t launch_direct<double>(const DirectItem *, int64_t, const double *, int64_t, const double *,
+                                          int64_t, const int32_t *, const void *, double *, double, hipStream_t);
+template hipError_t launch_finalize<float>(const double *, int64_t, const int32_t *, void *, int, hipStream_t);
+template hipError_t launch_finalize<double>(const double *, int64_t, const int32_t *, void *, int, hipStream_t);
+
+}  // namespace hvox
