@@ -73,8 +73,12 @@ typedef struct {
                                  0 -> 500e6 (the paper's default partition size, Table 2);
                                  +INFINITY -> one chunk per domain (monolithic type-3, Sect. 3). */
     double anisotropy;        /* alpha >= 1 of Algorithm 1; 0 -> 1. */
-    double upsampfac;         /* sigma, the grid upsampling factor; 0 -> 1.25 (the type-3 default
-                                 discussed in Sect. 5.2).  Accepted range [1.25, 2]. */
+    double upsampfac;         /* sigma, the upsampling of the spreading stage (grid 1 against the
+                                 Heisenberg box); 0 -> automatic: 1.25 (the type-3 default discussed
+                                 in Sect. 5.2), raised to 1.5 for eps < 5e-5 (float32) or eps < 5e-6
+                                 (float64), where 1.25 would cost digits.  Range [1.25, 2]. */
+    double inner_upsampfac;   /* sigma2, the upsampling of the inner FFT stage (grid 2 against grid 1);
+                                 0 -> 1.5.  Accepted range [1.25, 2]. */
     double direct_threshold;  /* per-sub-problem choice between NUFFT and direct summation (Sect. 3.1):
                                  < 0  -> automatic (cost model);  0 -> never direct (forced NUFFT);
                                  +INFINITY -> always direct.  A positive finite value t makes a
@@ -93,9 +97,13 @@ typedef struct {
 typedef struct {
     int64_t n_vis, n_pix;
     int32_t dtype;            /* hvox_dtype */
-    int32_t w;                /* kernel support (grid cells per dimension) */
-    double  beta;             /* exponential-of-semicircle shape parameter */
-    double  sigma;            /* upsampling factor */
+    int32_t w;                /* spreading kernel support (grid-1 cells per dimension) */
+    double  beta;             /* its exponential-of-semicircle shape parameter */
+    double  sigma;            /* spreading-stage upsampling factor */
+    int32_t w2;               /* interpolation kernel support (grid-2 cells) */
+    int32_t pad0;
+    double  beta2;            /* its shape parameter */
+    double  sigma2;           /* inner FFT upsampling factor */
     double  eps;              /* requested accuracy */
     double  h[3], eta[3];     /* Algorithm 1 maximum box dimensions (visibility, sky) */
     int32_t n_vis_chunks, n_sky_chunks;
@@ -137,7 +145,7 @@ typedef struct {
  * (on `stream`, synchronised before return): coordinates, permutations,
  * deconvolution and FFT tables.
  * eps == 0 selects direct summation for every sub-problem (the paper's eps=0
- * case).  eps floors: 1e-6 for HVOX_F32, 1e-10 for HVOX_F64.
+ * case).  eps floors: 1e-5 for HVOX_F32, 1e-10 for HVOX_F64.
  * n_vis or n_pix may be 0 (outputs are then all zero / empty).
  * On success *out receives the plan, owned by the caller (hvox_free).
  */

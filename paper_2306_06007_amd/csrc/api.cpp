@@ -227,7 +227,7 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
                 }));
             HVOX_TRY(timed(pl, HVOX_K_INTERP, st, [&] {
                 return launch_interp<T>(pairs, dd.pre_tgts + b.pre_tgts, np, b.tgts, txyz, n_tgt, dd.deconv, pl->ws,
-                                        pl->acc, p.w, p.beta, iota, st);
+                                        pl->acc, p.w2, p.beta2, iota, st);
             }));
         }
         if (!dp.direct.empty())
@@ -295,17 +295,24 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
     chk(upload(pl, hp.sky.perm, &pl->sky_perm, st), "sky permutation");
     if (rc) return rc;
 
-    // pre-correction tables 1 / Phi_hat(l / n2) (Gauss-Legendre, host)
-    const int nq = 2 * p.w + 60;
+    // Fourier transforms of the two ES kernels by Gauss-Legendre quadrature:
+    // K_hat(nu) = (w/2) sum_q a_q cos(pi nu w z_q), a_q = weight_q ES(z_q).
+    // Stage 1 (spreading, w/beta) deconvolves the targets; stage 2
+    // (interpolation, w2/beta2) pre-corrects the modes 1 / Phi_hat(l / n2).
+    const int nq = 2 * std::max(p.w, p.w2) + 60;
     std::vector<double> zq, wq;
     gauss_legendre(nq, &zq, &wq);
-    std::vector<double> aq(nq);
-    for (int q = 0; q < nq; ++q) aq[q] = wq[q] * std::exp(p.beta * (std::sqrt(1.0 - zq[q] * zq[q]) - 1.0));
+    std::vector<double> aq(nq), aq2(nq);
+    for (int q = 0; q < nq; ++q) {
+        const double root = std::sqrt(1.0 - zq[q] * zq[q]);
+        aq[q] = wq[q] * std::exp(p.beta * (root - 1.0));
+        aq2[q] = wq[q] * std::exp(p.beta2 * (root - 1.0));
+    }
     std::vector<double> precor(hp.precor_nu.size());
     for (size_t i = 0; i < precor.size(); ++i) {
         double s = 0.0;
-        for (int q = 0; q < nq; ++q) s += aq[q] * std::cos(M_PI * hp.precor_nu[i] * p.w * zq[q]);
-        precor[i] = 1.0 / (0.5 * p.w * s);
+        for (int q = 0; q < nq; ++q) s += aq2[q] * std::cos(M_PI * hp.precor_nu[i] * p.w2 * zq[q]);
+        precor[i] = 1.0 / (0.5 * p.w2 * s);
     }
     chk(upload(pl, precor, &pl->precor, st), "pre-correction tables");
     // twiddles exp(-2 pi i j / n); the host tables stay alive until the
@@ -442,8 +449,24 @@ int hvox_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t n_pix
     prm.eps = eps;
     hvox_opts o{};
     if (opts) o = *opts;
-    prm.sigma = o.upsampfac == 0.0 ? 1.25 : o.upsampfac;
+    // Upsampling factors.  Both type-3 stages divide by a kernel transform
+    // that falls by ~exp(-c(sigma) beta) per dimension towards the edge of its
+    // band (c = 0.27 at sigma = 1.25, 0.14 at 1.5): the deconvolution of
+    // targets near the corners of a box populated in all three dimensions,
+    // and the pre-correction of the inner FFT's edge modes, then recover
+    // their values from sums that cancel by that factor cubed, which costs
+    // digits of the working precision.  Measured on chunked 3D problems:
+    // sigma2 = 1.5 keeps the inner stage within eps for every supported eps;
+    // sigma = 1.25 for spreading holds down to 5e-5 (float32) and 5e-6
+    // (float64), and sigma = 1.5 below that.
+    if (o.upsampfac == 0.0)
+        prm.sigma = ((dtype == HVOX_F32 && eps > 0.0 && eps < 5e-5) || (dtype == HVOX_F64 && eps > 0.0 && eps < 5e-6))
+                        ? 1.5 : 1.25;
+    else
+        prm.sigma = o.upsampfac;
     if (!(prm.sigma >= 1.25 && prm.sigma <= 2.0)) return fail(HVOX_ERR_ARG, "upsampfac must lie in [1.25, 2]");
+    prm.sigma2 = o.inner_upsampfac == 0.0 ? 1.5 : o.inner_upsampfac;
+    if (!(prm.sigma2 >= 1.25 && prm.sigma2 <= 2.0)) return fail(HVOX_ERR_ARG, "inner_upsampfac must lie in [1.25, 2]");
     prm.alpha = o.anisotropy == 0.0 ? 1.0 : o.anisotropy;
     if (!(prm.alpha >= 1.0) || !std::isfinite(prm.alpha)) return fail(HVOX_ERR_ARG, "anisotropy must be >= 1");
     prm.max_fft_bytes = o.max_fft_bytes == 0.0 ? 500e6 : o.max_fft_bytes;
@@ -455,13 +478,14 @@ int hvox_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t n_pix
     prm.flags = o.flags;
     prm.all_direct = eps == 0.0 || std::isinf(prm.direct_threshold);
     if (eps > 0.0) {
-        const double floor_eps = dtype == HVOX_F64 ? 1e-10 : 1e-6;
+        const double floor_eps = dtype == HVOX_F64 ? 1e-10 : 1e-5;
         if (eps < floor_eps) return fail(HVOX_ERR_EPS, "eps below the floor of this dtype");
         int rc = es_params(std::min(eps, 0.5), prm.sigma, &prm.w, &prm.beta);
+        if (rc == HVOX_OK) rc = es_params(std::min(eps, 0.5), prm.sigma2, &prm.w2, &prm.beta2);
         if (rc) return fail(rc, "no kernel for this eps");
     } else {
-        prm.w = 3;
-        prm.beta = 1.0;
+        prm.w = prm.w2 = 3;
+        prm.beta = prm.beta2 = 1.0;
     }
     auto *pl = new (std::nothrow) hvox_plan_s();
     if (!pl) return fail(HVOX_ERR_OOM, "host allocation failed");
@@ -527,6 +551,9 @@ int hvox_plan_info(hvox_plan_t plan, hvox_plan_info_t *out)
     out->w = hp.prm.w;
     out->beta = hp.prm.beta;
     out->sigma = hp.prm.sigma;
+    out->w2 = hp.prm.w2;
+    out->beta2 = hp.prm.beta2;
+    out->sigma2 = hp.prm.sigma2;
     out->eps = hp.prm.eps;
     for (int d = 0; d < 3; ++d) { out->h[d] = hp.h[d]; out->eta[d] = hp.eta[d]; }
     out->n_vis_chunks = hp.vis.nc;

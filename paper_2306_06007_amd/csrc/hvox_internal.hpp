@@ -93,9 +93,12 @@ struct DirPlan {                         // one direction (synthesis or analysis
 struct Params {
     int dtype = HVOX_F32;
     double eps = 1e-4;
-    double sigma = 1.25;
-    int w = 8;
+    double sigma = 1.25;           // upsampling of the spreading stage (grid 1 vs the Heisenberg box)
+    int w = 8;                     // spreading kernel support (grid-1 cells)
     double beta = 0.0;
+    double sigma2 = 1.25;          // upsampling of the inner FFT stage (grid 2 vs grid 1)
+    int w2 = 8;                    // interpolation kernel support (grid-2 cells)
+    double beta2 = 0.0;
     bool all_direct = false;
     double direct_threshold = -1.0;
     double max_fft_bytes = 500e6;

@@ -423,14 +423,21 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
 // point x_S and target-tile reference s_T,
 //   s_k.x_n = s_k.x_S + s_T.(x_n - x_S) + (s_k - s_T).(x_n - x_S):
 // the first two terms are evaluated once per (target, tile) and
-// (source, tile) in float64; only the small third term is evaluated per
-// (target, source) pair, in the plan's precision.
+// (source, tile); only the small third term is evaluated per (target,
+// source) pair.  Phases are float64 (full rate on CDNA); the float32 plan
+// evaluates the reduced phase with the hardware sine / cosine, whose
+// argument is in revolutions.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void cis_rev_f32(float t, float &c, float &s)
+__device__ __forceinline__ void cis_rev(double t, float &c, float &s)
 {
-    float r = t - rintf(t);
+    const float r = static_cast<float>(t - rint(t));
     s = __builtin_amdgcn_sinf(r);
     c = __builtin_amdgcn_cosf(r);
+}
+__device__ __forceinline__ void cis_rev(double t, double &c, double &s)
+{
+    const double r = t - rint(t);
+    sincospi(2.0 * r, &s, &c);
 }
 
 template <typename T>
@@ -441,18 +448,17 @@ __global__ __launch_bounds__(kDirectTile) void k_direct(const DirectItem *__rest
                                                         const cplx<T> *__restrict__ in, double *__restrict__ acc,
                                                         double iota)
 {
-    __shared__ T lx[kDirectTile], ly[kDirectTile], lz[kDirectTile];
+    __shared__ double lx[kDirectTile], ly[kDirectTile], lz[kDirectTile];
     __shared__ cplx<T> lc[kDirectTile];
     const DirectItem it = items[blockIdx.x];
     const int tid = threadIdx.x;
     const bool has_t = tid < it.tgt_cnt;
     const int64_t k = it.tgt_off + (has_t ? tid : 0);
-    double sT[3], sk[3];
-    T sp[3];
+    double sT[3], sk[3], sp[3];
     for (int d = 0; d < 3; ++d) {
         sT[d] = txyz[d * ntgt + it.tgt_off];
         sk[d] = txyz[d * ntgt + k];
-        sp[d] = T(sk[d] - sT[d]);
+        sp[d] = sk[d] - sT[d];
     }
     const T sg = T(iota);
     double accr = 0.0, acci = 0.0;
@@ -470,9 +476,9 @@ __global__ __launch_bounds__(kDirectTile) void k_direct(const DirectItem *__rest
                 dxv[d] = sxyz[d * nsrc + n] - xS[d];
                 ph += sT[d] * dxv[d];
             }
-            lx[tid] = T(dxv[0]);
-            ly[tid] = T(dxv[1]);
-            lz[tid] = T(dxv[2]);
+            lx[tid] = dxv[0];
+            ly[tid] = dxv[1];
+            lz[tid] = dxv[2];
             const double2 e = cis_cycles(ph, iota);
             const cplx<T> c = in[perm[n]];
             lc[tid] = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
@@ -480,14 +486,9 @@ __global__ __launch_bounds__(kDirectTile) void k_direct(const DirectItem *__rest
         __syncthreads();
         T ar = T(0), ai = T(0);
         for (int j = 0; j < cnt; ++j) {
-            const T t = sp[0] * lx[j] + sp[1] * ly[j] + sp[2] * lz[j];
+            const double t = sp[0] * lx[j] + sp[1] * ly[j] + sp[2] * lz[j];
             T cs, sn;
-            if constexpr (sizeof(T) == 4) {
-                cis_rev_f32(t, cs, sn);
-            } else {
-                const T r = t - rint(t);
-                sincospi(T(2) * r, &sn, &cs);
-            }
+            cis_rev(t, cs, sn);
             sn *= sg;
             const cplx<T> c = lc[j];
             ar += c.x * cs - c.y * sn;

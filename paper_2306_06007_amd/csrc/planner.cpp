@@ -382,12 +382,14 @@ struct PairGeom {
 
 // Grid sizes of one sub-problem: source half-widths X, effective target
 // half-widths S (> 0).  Grid 1 holds the spread footprint of sources at
-// t = x' (2 sigma S), |t| <= T = 2 sigma S X, plus the kernel support; grid 2
-// upsamples it by sigma for the inner FFT; only the FFT outputs within
-// n2/(2 sigma) + w/2 of the origin are read by the interpolation, so only that
-// window is kept.
-PairGeom pair_geometry(const double X[3], const double S[3], double sigma, int w)
+// t = x' (2 sigma S), |t| <= T = 2 sigma S X, plus the kernel support w; grid
+// 2 upsamples it by the inner factor sigma2 for the FFT; only the FFT
+// outputs within n2/(2 sigma) + w2/2 of the origin are read by the
+// interpolation (kernel support w2), so only that window is kept.
+PairGeom pair_geometry(const double X[3], const double S[3], const Params &p)
 {
+    const double sigma = p.sigma, sigma2 = p.sigma2;
+    const int w = p.w, w2 = p.w2;
     PairGeom g{};
     g.fits = true;
     for (int d = 0; d < 3; ++d) {
@@ -395,10 +397,10 @@ PairGeom pair_geometry(const double X[3], const double S[3], double sigma, int w
         double need1 = std::ceil(2.0 * T + w + 2.0);
         if (!(need1 < 1e9)) { g.fits = false; need1 = 1e9; }
         g.n1[d] = smooth_even(static_cast<int64_t>(need1));
-        int64_t need2 = static_cast<int64_t>(std::ceil(sigma * g.n1[d]));
-        g.n2[d] = smooth_even(std::max<int64_t>(need2, 2 * w));
+        int64_t need2 = static_cast<int64_t>(std::ceil(sigma2 * g.n1[d]));
+        g.n2[d] = smooth_even(std::max<int64_t>(need2, 2 * w2));
         if (g.n2[d] > kFftMaxLen) g.fits = false;
-        int64_t R = static_cast<int64_t>(std::ceil(g.n2[d] / (2.0 * sigma) + 0.5 * w)) + 1;
+        int64_t R = static_cast<int64_t>(std::ceil(g.n2[d] / (2.0 * sigma) + 0.5 * w2)) + 1;
         if (2 * R + 1 >= g.n2[d]) { g.wstart[d] = 0; g.wcount[d] = g.n2[d]; }
         else { g.wstart[d] = static_cast<int32_t>(-R); g.wcount[d] = static_cast<int32_t>(2 * R + 1); }
         g.kscale[d] = 2.0 * sigma * S[d];
@@ -433,14 +435,14 @@ struct DirInputs {
     double s_floor[3];          // minimum effective target half-width per dimension
 };
 
-double pair_nufft_seconds(const PairGeom &g, int64_t ns, int64_t nt, int w, int dtype, double *bytes)
+double pair_nufft_seconds(const PairGeom &g, int64_t ns, int64_t nt, const Params &p, double *bytes)
 {
-    const Rates r = rates_for(dtype);
-    const double delta = dtype == HVOX_F64 ? 16.0 : 8.0;
+    const Rates r = rates_for(p.dtype);
+    const double delta = p.dtype == HVOX_F64 ? 16.0 : 8.0;
     double b = delta * (static_cast<double>(g.bufA) + g.g1 + 2.0 * g.bx + 2.0 * g.cy + g.dz);
     if (bytes) *bytes = b;
-    double w3 = static_cast<double>(w) * w * w;
-    return b / r.hbm_bytes_per_s + (static_cast<double>(ns) + nt) * w3 / r.cells_per_s + r.pair_overhead_s;
+    const double w3 = static_cast<double>(p.w) * p.w * p.w, w23 = static_cast<double>(p.w2) * p.w2 * p.w2;
+    return b / r.hbm_bytes_per_s + (ns * w3 + nt * w23) / r.cells_per_s + r.pair_overhead_s;
 }
 
 double pair_direct_seconds(int64_t ns, int64_t nt, int dtype)
@@ -456,6 +458,7 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
     const ChunkSet &src = *in.src, &tgt = *in.tgt;
     const double delta = p.dtype == HVOX_F64 ? 16.0 : 8.0;
     const double w3 = static_cast<double>(p.w) * p.w * p.w;
+    const double w23 = static_cast<double>(p.w2) * p.w2 * p.w2;
     struct Cand { int32_t i, j; PairGeom g; };
     std::vector<Cand> nufft;
     dp->direct.clear();
@@ -469,9 +472,9 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
         const int64_t nt = tgt.off[j + 1] - tgt.off[j];
         for (int32_t i = 0; i < src.nc; ++i) {
             const int64_t ns = src.off[i + 1] - src.off[i];
-            PairGeom g = pair_geometry(&src.half[3 * i], S, p.sigma, p.w);
+            PairGeom g = pair_geometry(&src.half[3 * i], S, p);
             double t_dir = pair_direct_seconds(ns, nt, p.dtype);
-            double t_nu = pair_nufft_seconds(g, ns, nt, p.w, p.dtype, nullptr);
+            double t_nu = pair_nufft_seconds(g, ns, nt, p, nullptr);
             bool direct;
             if (p.all_direct || !g.fits) direct = true;
             else if (p.direct_threshold == 0.0) direct = false;
@@ -585,9 +588,9 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
             dp->alg_bytes[HVOX_K_FFT_Y] += delta * (static_cast<double>(g.bx) + g.cy);
             dp->alg_bytes[HVOX_K_FFT_Z] += delta * (static_cast<double>(g.cy) + g.dz);
             dp->alg_bytes[HVOX_K_INTERP] += pd.tgt_cnt * (24.0 + 8.0 + 16.0) +
-                                            delta * std::min(static_cast<double>(g.dz), pd.tgt_cnt * w3);
+                                            delta * std::min(static_cast<double>(g.dz), pd.tgt_cnt * w23);
             dp->alg_flops[HVOX_K_SPREAD] += pd.src_cnt * w3;
-            dp->alg_flops[HVOX_K_INTERP] += pd.tgt_cnt * w3;
+            dp->alg_flops[HVOX_K_INTERP] += pd.tgt_cnt * w23;
             dp->pairs.push_back(pd);
         }
         b.ws_end = offB;
@@ -639,7 +642,7 @@ int make_host_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t 
         if (rc != HVOX_OK) { *err = "Algorithm 1 rejected its inputs"; return rc; }
         double X[3], S[3];
         for (int d = 0; d < 3; ++d) { X[d] = 0.5 * hp->eta[d]; S[d] = 0.5 * hp->h[d]; }
-        PairGeom g = pair_geometry(X, S, p.sigma, p.w);
+        PairGeom g = pair_geometry(X, S, p);
         bool ok = g.fits && (!std::isfinite(budget) || ws_of(g) * delta <= budget);
         if (ok) break;
         double shrink = 0.7;
@@ -690,7 +693,7 @@ int make_host_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t 
             double S[3];
             for (int d = 0; d < 3; ++d) S[d] = std::max(in->tgt->half[3 * j + d], in->s_floor[d]);
             for (int32_t i = 0; i < in->src->nc; ++i) {
-                PairGeom g = pair_geometry(&in->src->half[3 * i], S, p.sigma, p.w);
+                PairGeom g = pair_geometry(&in->src->half[3 * i], S, p);
                 if (g.fits) max_ws = std::max(max_ws, ws_of(g));
             }
         }

@@ -38,6 +38,7 @@ class HvoxOpts(ctypes.Structure):
     _fields_ = [("max_fft_bytes", ctypes.c_double),
                 ("anisotropy", ctypes.c_double),
                 ("upsampfac", ctypes.c_double),
+                ("inner_upsampfac", ctypes.c_double),
                 ("direct_threshold", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_double),
                 ("vis_chunk", ctypes.POINTER(ctypes.c_int32)),
@@ -49,7 +50,9 @@ class HvoxOpts(ctypes.Structure):
 class HvoxPlanInfo(ctypes.Structure):
     _fields_ = [("n_vis", ctypes.c_int64), ("n_pix", ctypes.c_int64),
                 ("dtype", ctypes.c_int32), ("w", ctypes.c_int32),
-                ("beta", ctypes.c_double), ("sigma", ctypes.c_double), ("eps", ctypes.c_double),
+                ("beta", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("w2", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("beta2", ctypes.c_double), ("sigma2", ctypes.c_double), ("eps", ctypes.c_double),
                 ("h", ctypes.c_double * 3), ("eta", ctypes.c_double * 3),
                 ("n_vis_chunks", ctypes.c_int32), ("n_sky_chunks", ctypes.c_int32),
                 ("n_pairs_nufft", ctypes.c_int64), ("n_pairs_direct", ctypes.c_int64),
@@ -187,7 +190,8 @@ class Plan:
     "f64", shaped (n,) or (ntrans, n)."""
 
     def __init__(self, uvw, xyz, eps: float, dtype: str = "f32", *, max_fft_bytes: float = 0.0,
-                 anisotropy: float = 0.0, upsampfac: float = 0.0, direct_threshold: float = -1.0,
+                 anisotropy: float = 0.0, upsampfac: float = 0.0, inner_upsampfac: float = 0.0,
+                 direct_threshold: float = -1.0,
                  workspace_bytes: float = 0.0, vis_chunk=None, sky_chunk=None, real_sky: bool = False,
                  host_only: bool = False, timing: bool = False, stream=None):
         self._lib = load_library()
@@ -203,6 +207,7 @@ class Plan:
         opts.max_fft_bytes = max_fft_bytes
         opts.anisotropy = anisotropy
         opts.upsampfac = upsampfac
+        opts.inner_upsampfac = inner_upsampfac
         opts.direct_threshold = direct_threshold
         opts.workspace_bytes = workspace_bytes
         keep = []

@@ -66,7 +66,7 @@ def test_compact_disk_monolithic_nufft(dtype, eps):
     assert es <= eps and ea <= eps
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 2e-6)])
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-6)])
 def test_compact_disk_all_direct(dtype, tol):
     wl = W.compact_disk()
     eps = 0.0 if dtype == "f64" else 1e-4
@@ -100,8 +100,8 @@ def test_chunked_auto(dtype, eps):
     assert es <= eps and ea <= eps
 
 
-@pytest.mark.parametrize("dtype,eps", [("f64", 1e-2), ("f64", 1e-4), ("f64", 1e-7), ("f64", 1e-10),
-                                       ("f32", 1e-2), ("f32", 1e-3), ("f32", 1e-5), ("f32", 1e-6)])
+@pytest.mark.parametrize("dtype,eps", [("f64", 1e-2), ("f64", 1e-4), ("f64", 1e-7), ("f64", 1e-8), ("f64", 1e-10),
+                                       ("f32", 1e-2), ("f32", 1e-3), ("f32", 3e-5), ("f32", 1e-5)])
 def test_eps_sweep(dtype, eps):
     """Accuracy compliance over requested eps (the paper's Sect. 5.2 study):
     achieved error <= requested, in the monolithic and the chunked case."""
@@ -158,9 +158,10 @@ def test_ntrans_batch_equals_loop():
     with hv.Plan(wl.uvw, wl.xyz, 1e-6, "f64", max_fft_bytes=4e6) as p:
         Vb = _np(p.synthesis(_t(wl.sky, "f64")))
         Ib = _np(p.analysis(_t(wl.vis, "f64")))
+        # same launches row by row; only the order of float64 atomic additions may differ
         for t in range(3):
-            assert np.array_equal(Vb[t], _np(p.synthesis(_t(wl.sky[t], "f64"))))
-            assert np.array_equal(Ib[t], _np(p.analysis(_t(wl.vis[t], "f64"))))
+            assert oracle.rel_l2(Vb[t], _np(p.synthesis(_t(wl.sky[t], "f64")))) < 1e-13
+            assert oracle.rel_l2(Ib[t], _np(p.analysis(_t(wl.vis[t], "f64")))) < 1e-13
     Vref = oracle.synthesis(wl.uvw, wl.xyz, wl.sky)
     assert oracle.rel_l2(Vb, Vref) <= 1e-6
 
