@@ -182,6 +182,11 @@ int hvox_plan_chunks(hvox_plan_t plan, int32_t *vis_chunk, int32_t *sky_chunk);
 int hvox_stats(hvox_plan_t plan, hvox_stats_t *out);
 int hvox_stats_reset(hvox_plan_t plan);
 
+/* Switch per-launch HIP-event timing on (1) or off (0) for later calls of
+ * this plan (the HVOX_TIMING flag sets the initial state).  Timing adds two
+ * event records per kernel launch on the call's stream. */
+int hvox_set_timing(hvox_plan_t plan, int32_t on);
+
 /* ---- host-only helpers (no GPU needed) --------------------------------- */
 
 /* Kernel parameters for accuracy eps at upsampling sigma: support w (cells)

@@ -607,6 +607,14 @@ int hvox_stats(hvox_plan_t plan, hvox_stats_t *out)
     return HVOX_OK;
 }
 
+int hvox_set_timing(hvox_plan_t plan, int32_t on)
+{
+    if (!plan) return fail(HVOX_ERR_ARG, "NULL plan");
+    if (on) plan->hp.prm.flags |= HVOX_TIMING;
+    else plan->hp.prm.flags &= ~HVOX_TIMING;
+    return HVOX_OK;
+}
+
 int hvox_stats_reset(hvox_plan_t plan)
 {
     if (!plan) return fail(HVOX_ERR_ARG, "NULL plan");

@@ -69,7 +69,7 @@ class HvoxStats(ctypes.Structure):
 
 
 EXPORTS = ("hvox_plan", "hvox_synthesis", "hvox_analysis", "hvox_free", "hvox_plan_info",
-           "hvox_plan_permutation", "hvox_plan_chunks", "hvox_stats", "hvox_stats_reset",
+           "hvox_plan_permutation", "hvox_plan_chunks", "hvox_stats", "hvox_stats_reset", "hvox_set_timing",
            "hvox_kernel_params", "hvox_alg1", "hvox_partition", "hvox_error_string",
            "hvox_last_error", "hvox_version")
 
@@ -107,6 +107,8 @@ def load_library():
     lib.hvox_stats.argtypes = [vp, ctypes.POINTER(HvoxStats)]
     lib.hvox_stats_reset.restype = ctypes.c_int
     lib.hvox_stats_reset.argtypes = [vp]
+    lib.hvox_set_timing.restype = ctypes.c_int
+    lib.hvox_set_timing.argtypes = [vp, ctypes.c_int32]
     lib.hvox_kernel_params.restype = ctypes.c_int
     lib.hvox_kernel_params.argtypes = [ctypes.c_double, ctypes.c_double, ip, dp]
     lib.hvox_alg1.restype = ctypes.c_int
@@ -328,6 +330,9 @@ class Plan:
 
     def reset_stats(self):
         _check(self._lib.hvox_stats_reset(self._plan))
+
+    def set_timing(self, on: bool):
+        _check(self._lib.hvox_set_timing(self._plan, 1 if on else 0))
 
     def free(self):
         if self._plan.value is not None:
