@@ -75,8 +75,9 @@ typedef struct {
     double anisotropy;        /* alpha >= 1 of Algorithm 1; 0 -> 1. */
     double upsampfac;         /* sigma, the upsampling of the spreading stage (grid 1 against the
                                  Heisenberg box); 0 -> automatic: 1.25 (the type-3 default discussed
-                                 in Sect. 5.2), raised to 1.5 for eps < 5e-5 (float32) or eps < 5e-6
-                                 (float64), where 1.25 would cost digits.  Range [1.25, 2]. */
+                                 in Sect. 5.2) while its kernel support stays <= 8 (float32) or
+                                 <= 12 (float64) cells, else 1.5, where 1.25 would cost digits of the
+                                 working precision.  Range [1.25, 2]. */
     double inner_upsampfac;   /* sigma2, the upsampling of the inner FFT stage (grid 2 against grid 1);
                                  0 -> 1.5.  Accepted range [1.25, 2]. */
     double direct_threshold;  /* per-sub-problem choice between NUFFT and direct summation (Sect. 3.1):
@@ -105,6 +106,7 @@ typedef struct {
     double  beta2;            /* its shape parameter */
     double  sigma2;           /* inner FFT upsampling factor */
     double  eps;              /* requested accuracy */
+    double  eps_sub;          /* accuracy the sub-problem kernels are sized for (eps / min(4, chunks)) */
     double  h[3], eta[3];     /* Algorithm 1 maximum box dimensions (visibility, sky) */
     int32_t n_vis_chunks, n_sky_chunks;
     int64_t n_pairs_nufft, n_pairs_direct;

@@ -19,9 +19,13 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t st);
 hipError_t launch_deconv(const double *xyz, int64_t n, const int32_t *chunk_of, const double *ctr,
                          const double *hscale, const double *zq, const double *aq, int nq, int w, double *out,
                          hipStream_t st);
+hipError_t launch_bin(const PairDev *pairs, const int64_t *prefix, int npairs, int64_t total, const double *xyz,
+                      int64_t nsrc, int w, int32_t *counts, unsigned long long *cursor, int32_t *records,
+                      hipStream_t st);
 template <typename T>
-hipError_t launch_spread(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t, const int32_t *,
-                         const void *, void *, int, double, double, hipStream_t);
+hipError_t launch_spread(const PairDev *, const int64_t *, int, int64_t, const int64_t *, const int32_t *,
+                         const double *, int64_t, const int32_t *, const void *, void *, int, double, double,
+                         hipStream_t);
 template <typename T>
 hipError_t launch_fft(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *, const double *, int,
                       double, hipStream_t);
@@ -49,6 +53,9 @@ struct DevDir {
     int64_t *pre_pts = nullptr, *pre_tgts = nullptr, *pre_tiles[3] = {nullptr, nullptr, nullptr};
     DirectItem *direct = nullptr;
     double *deconv = nullptr;        // per chunk-order target
+    int64_t *pre_stiles = nullptr;   // per batch: tile prefix over its pairs
+    int64_t *tile_off = nullptr;     // [tiles_total + 1] record offsets of every grid-1 tile
+    int32_t *records = nullptr;      // source indices listed per tile (plan-resident binning)
 };
 
 struct TimedLaunch {
@@ -211,14 +218,9 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
         for (const Batch &b : dp.batches) {
             const PairDev *pairs = dd.pairs + b.pair0;
             const int np = static_cast<int>(b.npairs);
-            HVOX_TRY(timed(pl, HVOX_K_ZERO, st, [&] {
-                // the batch's grid-1 buffers, counted in doubles (complex = 1 or 2 doubles)
-                return launch_zero(reinterpret_cast<double *>(static_cast<C *>(pl->ws) + b.zero_off),
-                                   b.zero_cnt * static_cast<int64_t>(sizeof(C) / sizeof(double)), st);
-            }));
             HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
-                return launch_spread<T>(pairs, dd.pre_pts + b.pre_pts, np, b.pts, sxyz, n_src, sperm, in_t, pl->ws,
-                                        p.w, p.beta, iota, st);
+                return launch_spread<T>(pairs, dd.pre_stiles + b.pre_stiles, np, b.stiles, dd.tile_off, dd.records,
+                                        sxyz, n_src, sperm, in_t, pl->ws, p.w, p.beta, iota, st);
             }));
             for (int pass = 0; pass < 3; ++pass)
                 HVOX_TRY(timed(pl, HVOX_K_FFT_X + pass, st, [&] {
@@ -273,6 +275,60 @@ int upload_dir(hvox_plan_s *pl, const DirPlan &dp, DevDir *dd, hipStream_t st)
     for (int q = 0; q < 3; ++q)
         if ((e = upload(pl, dp.pre_tiles[q], &dd->pre_tiles[q], st)) != hipSuccess) return HVOX_ERR_OOM;
     if ((e = upload(pl, dp.direct, &dd->direct, st)) != hipSuccess) return HVOX_ERR_OOM;
+    if ((e = upload(pl, dp.pre_stiles, &dd->pre_stiles, st)) != hipSuccess) return HVOX_ERR_OOM;
+    return HVOX_OK;
+}
+
+// Plan-time binning of every NUFFT sub-problem's sources to the grid-1 tiles
+// their footprints touch (count, host prefix sum, scatter); the per-tile
+// lists stay resident and drive the tiled spreading kernel.
+int bin_direction(hvox_plan_s *pl, const DirPlan &dp, DevDir *dd, const double *sxyz, int64_t n_src, hipStream_t st,
+                  std::string *err)
+{
+    if (dp.tiles_total == 0) return HVOX_OK;
+    const int w = pl->hp.prm.w;
+    const int64_t nt = dp.tiles_total;
+    void *d_counts = nullptr, *d_cursor = nullptr;
+    auto cleanup = [&]() {
+        if (d_counts) (void)hipFree(d_counts);
+        if (d_cursor) (void)hipFree(d_cursor);
+    };
+    auto bad = [&](hipError_t e, const char *what) {
+        cleanup();
+        *err = std::string(what) + ": " + hipGetErrorString(e);
+        return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? HVOX_ERR_OOM : HVOX_ERR_HIP;
+    };
+    hipError_t e = hipMalloc(&d_counts, sizeof(int32_t) * nt);
+    if (e != hipSuccess) return bad(e, "binning counts");
+    e = hipMemsetAsync(d_counts, 0, sizeof(int32_t) * nt, st);
+    for (const Batch &b : dp.batches) {
+        if (e != hipSuccess) break;
+        e = launch_bin(dd->pairs + b.pair0, dd->pre_pts + b.pre_pts, static_cast<int>(b.npairs), b.pts, sxyz, n_src,
+                       w, static_cast<int32_t *>(d_counts), nullptr, nullptr, st);
+    }
+    std::vector<int32_t> counts(nt);
+    if (e == hipSuccess) e = hipMemcpyAsync(counts.data(), d_counts, sizeof(int32_t) * nt, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bad(e, "binning count pass");
+    std::vector<int64_t> off(nt + 1, 0);
+    for (int64_t i = 0; i < nt; ++i) off[i + 1] = off[i] + counts[i];
+    e = upload(pl, off, &dd->tile_off, st);
+    if (e != hipSuccess) return bad(e, "tile offsets");
+    void *rec = nullptr;
+    e = dev_alloc(pl, sizeof(int32_t) * std::max<int64_t>(off[nt], 1), &rec, true);
+    if (e != hipSuccess) return bad(e, "tile records");
+    dd->records = static_cast<int32_t *>(rec);
+    e = hipMalloc(&d_cursor, sizeof(unsigned long long) * nt);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_cursor, dd->tile_off, sizeof(int64_t) * nt, hipMemcpyDeviceToDevice, st);
+    for (const Batch &b : dp.batches) {
+        if (e != hipSuccess) break;
+        e = launch_bin(dd->pairs + b.pair0, dd->pre_pts + b.pre_pts, static_cast<int>(b.npairs), b.pts, sxyz, n_src,
+                       w, nullptr, static_cast<unsigned long long *>(d_cursor), dd->records, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bad(e, "binning scatter pass");
+    cleanup();
     return HVOX_OK;
 }
 
@@ -345,6 +401,9 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
         *err = "device allocation of sub-problem tables failed";
         return HVOX_ERR_OOM;
     }
+    rc = bin_direction(pl, hp.syn, &pl->syn, pl->sky_xyz, hp.n_pix, st, err);
+    if (rc == HVOX_OK) rc = bin_direction(pl, hp.ana, &pl->ana, pl->vis_xyz, hp.n_vis, st, err);
+    if (rc) return rc;
 
     // deconvolution factors of every target, per direction
     double *d_zq = nullptr, *d_aq = nullptr, *d_ctr_v = nullptr, *d_ctr_s = nullptr, *d_hs_v = nullptr,
@@ -449,24 +508,12 @@ int hvox_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t n_pix
     prm.eps = eps;
     hvox_opts o{};
     if (opts) o = *opts;
-    // Upsampling factors.  Both type-3 stages divide by a kernel transform
-    // that falls by ~exp(-c(sigma) beta) per dimension towards the edge of its
-    // band (c = 0.27 at sigma = 1.25, 0.14 at 1.5): the deconvolution of
-    // targets near the corners of a box populated in all three dimensions,
-    // and the pre-correction of the inner FFT's edge modes, then recover
-    // their values from sums that cancel by that factor cubed, which costs
-    // digits of the working precision.  Measured on chunked 3D problems:
-    // sigma2 = 1.5 keeps the inner stage within eps for every supported eps;
-    // sigma = 1.25 for spreading holds down to 5e-5 (float32) and 5e-6
-    // (float64), and sigma = 1.5 below that.
-    if (o.upsampfac == 0.0)
-        prm.sigma = ((dtype == HVOX_F32 && eps > 0.0 && eps < 5e-5) || (dtype == HVOX_F64 && eps > 0.0 && eps < 5e-6))
-                        ? 1.5 : 1.25;
-    else
-        prm.sigma = o.upsampfac;
-    if (!(prm.sigma >= 1.25 && prm.sigma <= 2.0)) return fail(HVOX_ERR_ARG, "upsampfac must lie in [1.25, 2]");
-    prm.sigma2 = o.inner_upsampfac == 0.0 ? 1.5 : o.inner_upsampfac;
-    if (!(prm.sigma2 >= 1.25 && prm.sigma2 <= 2.0)) return fail(HVOX_ERR_ARG, "inner_upsampfac must lie in [1.25, 2]");
+    prm.sigma_opt = o.upsampfac;
+    prm.sigma2_opt = o.inner_upsampfac;
+    if (prm.sigma_opt != 0.0 && !(prm.sigma_opt >= 1.25 && prm.sigma_opt <= 2.0))
+        return fail(HVOX_ERR_ARG, "upsampfac must lie in [1.25, 2]");
+    if (prm.sigma2_opt != 0.0 && !(prm.sigma2_opt >= 1.25 && prm.sigma2_opt <= 2.0))
+        return fail(HVOX_ERR_ARG, "inner_upsampfac must lie in [1.25, 2]");
     prm.alpha = o.anisotropy == 0.0 ? 1.0 : o.anisotropy;
     if (!(prm.alpha >= 1.0) || !std::isfinite(prm.alpha)) return fail(HVOX_ERR_ARG, "anisotropy must be >= 1");
     prm.max_fft_bytes = o.max_fft_bytes == 0.0 ? 500e6 : o.max_fft_bytes;
@@ -480,10 +527,11 @@ int hvox_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t n_pix
     if (eps > 0.0) {
         const double floor_eps = dtype == HVOX_F64 ? 1e-10 : 1e-5;
         if (eps < floor_eps) return fail(HVOX_ERR_EPS, "eps below the floor of this dtype");
-        int rc = es_params(std::min(eps, 0.5), prm.sigma, &prm.w, &prm.beta);
-        if (rc == HVOX_OK) rc = es_params(std::min(eps, 0.5), prm.sigma2, &prm.w2, &prm.beta2);
+        int rc = choose_kernels(&prm, eps);
         if (rc) return fail(rc, "no kernel for this eps");
     } else {
+        prm.sigma = prm.sigma_opt > 0.0 ? prm.sigma_opt : 1.25;
+        prm.sigma2 = prm.sigma2_opt > 0.0 ? prm.sigma2_opt : 1.5;
         prm.w = prm.w2 = 3;
         prm.beta = prm.beta2 = 1.0;
     }
@@ -555,6 +603,7 @@ int hvox_plan_info(hvox_plan_t plan, hvox_plan_info_t *out)
     out->beta2 = hp.prm.beta2;
     out->sigma2 = hp.prm.sigma2;
     out->eps = hp.prm.eps;
+    out->eps_sub = hp.prm.eps_sub > 0.0 ? hp.prm.eps_sub : hp.prm.eps;
     for (int d = 0; d < 3; ++d) { out->h[d] = hp.h[d]; out->eta[d] = hp.eta[d]; }
     out->n_vis_chunks = hp.vis.nc;
     out->n_sky_chunks = hp.sky.nc;

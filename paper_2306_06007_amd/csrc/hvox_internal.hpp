@@ -18,8 +18,13 @@ constexpr int kFftMaxLen = 4096;     // longest 1D FFT (one line must fit a work
 constexpr int kFftMaxLines = 64;     // lines per FFT workgroup
 constexpr int kDirectTile = 256;     // targets per direct-sum workgroup (one per thread)
 constexpr int kDirectSeg = 2048;     // sources per direct-sum work item
-constexpr int kWavesPerBlock = 4;    // spread / interp: one wavefront per point
+constexpr int kWavesPerBlock = 4;    // interp: one wavefront per target
 constexpr int kMaxStages = 16;       // radix stages per FFT length
+// spreading gathers by grid-1 tile: one 256-thread workgroup per tile of
+// kTileX x kTileY x kTileZ cells, each thread owning one x-y column of kTileZ
+// cells; points touching the tile are staged kSpreadBatch at a time in LDS
+constexpr int kTileX = 32, kTileY = 8, kTileZ = 8;
+constexpr int kSpreadBatch = 64;
 
 // ---- one type-3 sub-problem (source chunk -> target chunk) on the device ---
 // Sub-problem math (Sect. 3, the four type-3 steps; centring as in the
@@ -43,6 +48,9 @@ struct PairDev {
     int32_t nrad[3];             // radix stages per dimension
     int32_t lines_per_tile[3];   // FFT lines per workgroup, per pass
     int64_t bufA, bufB;          // complex-element offsets of the two grid buffers in the workspace
+    int64_t tile0;               // index of the pair's first grid-1 tile among the direction's tiles
+    int32_t ntile[3];            // grid-1 tiles per dimension
+    int32_t pad_;
     int64_t precor[3];           // offsets into the pre-correction table (n1[d] entries each)
     int64_t tw[3];               // offsets into the twiddle table (n2[d] entries each)
     uint8_t radix[3][kMaxStages];
@@ -71,7 +79,8 @@ struct Batch {
     int64_t pair0 = 0, npairs = 0;       // range in the direction's PairDev array
     int64_t pts = 0, tgts = 0;           // spread points, interp targets
     int64_t tiles[3] = {0, 0, 0};        // FFT workgroups per pass
-    int64_t zero_off = 0, zero_cnt = 0;  // workspace range (complex elements) to clear before spreading
+    int64_t stiles = 0;                  // spreading tiles (workgroups)
+    int64_t pre_stiles = 0;              // offset of the batch's tile prefix array
     int64_t ws_end = 0;                  // end of the batch's workspace use (complex elements)
     int64_t pre_pts = 0, pre_tgts = 0;   // offsets into the prefix arrays
     int64_t pre_tiles[3] = {0, 0, 0};
@@ -83,6 +92,8 @@ struct DirPlan {                         // one direction (synthesis or analysis
     std::vector<PairDev> pairs;          // NUFFT sub-problems, batch-contiguous
     std::vector<Batch> batches;
     std::vector<int64_t> pre_pts, pre_tgts, pre_tiles[3];   // per batch: npairs+1 prefix sums
+    std::vector<int64_t> pre_stiles;     // per batch: npairs+1 prefix sums of spreading tiles
+    int64_t tiles_total = 0;             // spreading tiles over all batches
     std::vector<DirectItem> direct;
     double grid_cells = 0.0, direct_terms = 0.0;
     double est_seconds = 0.0;
@@ -93,9 +104,12 @@ struct DirPlan {                         // one direction (synthesis or analysis
 struct Params {
     int dtype = HVOX_F32;
     double eps = 1e-4;
+    double eps_sub = 0.0;          // accuracy each sub-problem's kernels are sized for (0: eps)
     double sigma = 1.25;           // upsampling of the spreading stage (grid 1 vs the Heisenberg box)
     int w = 8;                     // spreading kernel support (grid-1 cells)
     double beta = 0.0;
+    double sigma_opt = 0.0;        // caller's spreading upsampling (0: automatic)
+    double sigma2_opt = 0.0;       // caller's inner-FFT upsampling (0: automatic)
     double sigma2 = 1.25;          // upsampling of the inner FFT stage (grid 2 vs grid 1)
     int w2 = 8;                    // interpolation kernel support (grid-2 cells)
     double beta2 = 0.0;
@@ -128,6 +142,7 @@ struct HostPlan {
 
 // ---- planner entry points (planner.cpp, host only) ------------------------
 int es_params(double eps, double sigma, int *w, double *beta);
+int choose_kernels(Params *p, double eps_sub);
 int alg1(const double B[3], const double P[3], double v_max, double alpha, double h[3], double eta[3]);
 int64_t partition(const double *x, int64_t n, const double h[3], int32_t *labels);
 int make_host_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t n_pix,

@@ -104,72 +104,145 @@ __global__ void k_deconv(const double *__restrict__ xyz, int64_t n, const int32_
 
 // ---------------------------------------------------------------------------
 // spreading (type-3 step 1, "spreading ... followed by tapering" of Sect. 3):
-//   b_l += c'_n prod_d ES((l_d - t_nd) 2/w),  c'_n = c_n exp(2 pi i iota s_c.x'_n)
-// One wavefront per source point; the lanes cover the w x w (x, y) rows of
-// its footprint and loop over z, adding with float atomics (the footprints
-// of neighbouring points are disjoint in the sparse regime this path serves,
-// so each row is a short contiguous run of one cache line or two).
+//   b_l = sum_n c'_n prod_d ES((l_d - t_nd) 2/w),  c'_n = c_n exp(2 pi i iota s_c.x'_n),
+// with t_n = (x_n - x_c) * kscale (grid-1 units) and l in [-n1/2, n1/2)^3.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pairs, const int64_t *__restrict__ prefix,
-                                                int npairs, int64_t total, const double *__restrict__ xyz, int64_t nsrc,
-                                                const int32_t *__restrict__ perm, const cplx<T> *__restrict__ in,
-                                                cplx<T> *__restrict__ ws, int w, T beta, double iota)
+
+// grid-1 footprint of a source: first cell (local index l + n1/2) and the
+// float64 grid coordinate; shared by the binning and the spreading kernels so
+// that both see exactly the same cells.
+__device__ __forceinline__ void source_footprint(const PairDev &P, const double *__restrict__ xyz, int64_t nsrc,
+                                                 int64_t n, int w, double xp[3], double t[3], int c0[3])
 {
-    __shared__ T ker[kWavesPerBlock][3 * kWMax];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int d = 0; d < 3; ++d) {
+        xp[d] = xyz[d * nsrc + n] - P.xc[d];
+        t[d] = xp[d] * P.kscale[d];
+        c0[d] = (int)ceil(t[d] - 0.5 * w) + P.n1[d] / 2;
+    }
+}
+
+// Plan-time binning: every (sub-problem, source) pair is listed under each
+// grid-1 tile its w^3 footprint touches.  Pass 1 (cursor == nullptr)
+// counts, pass 2 scatters source indices to the offsets the host computed.
+__global__ void k_bin_points(const PairDev *__restrict__ pairs, const int64_t *__restrict__ prefix, int npairs,
+                             int64_t total, const double *__restrict__ xyz, int64_t nsrc, int w,
+                             int32_t *__restrict__ counts, unsigned long long *__restrict__ cursor,
+                             int32_t *__restrict__ records)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int p = (int)find_segment(prefix, npairs, g);
+    const PairDev &P = pairs[p];
+    const int64_t n = P.src_off + (g - prefix[p]);
+    double xp[3], t[3];
+    int c0[3];
+    source_footprint(P, xyz, nsrc, n, w, xp, t, c0);
+    const int tdim[3] = {kTileX, kTileY, kTileZ};
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = max(0, c0[d]) / tdim[d];
+        hi[d] = min(P.n1[d] - 1, c0[d] + w - 1);
+        hi[d] = hi[d] < 0 ? -1 : hi[d] / tdim[d];
+        hi[d] = min(hi[d], P.ntile[d] - 1);
+    }
+    for (int tz = lo[2]; tz <= hi[2]; ++tz)
+        for (int ty = lo[1]; ty <= hi[1]; ++ty)
+            for (int tx = lo[0]; tx <= hi[0]; ++tx) {
+                const int64_t tile = P.tile0 + ((int64_t)tz * P.ntile[1] + ty) * P.ntile[0] + tx;
+                if (cursor == nullptr) {
+                    atomicAdd(counts + tile, 1);
+                } else {
+                    const unsigned long long pos = atomicAdd(cursor + tile, 1ull);
+                    records[pos] = (int32_t)n;
+                }
+            }
+}
+
+// One workgroup per grid-1 tile.  Thread (x, y) of the 32 x 8 face owns the
+// kTileZ cells of its column; the tile's sources are staged kSpreadBatch at a
+// time (their pre-phased values, footprint origin and 3w kernel values in
+// LDS), every thread adds the contributions that fall in its cells, and the
+// whole tile is written once (empty tiles write zeros: no separate clearing
+// pass, no atomics, and for a given plan the result is deterministic).
+template <typename T>
+__global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pairs, const int64_t *__restrict__ tprefix,
+                                                int npairs, const int64_t *__restrict__ toff,
+                                                const int32_t *__restrict__ records, const double *__restrict__ xyz,
+                                                int64_t nsrc, const int32_t *__restrict__ perm,
+                                                const cplx<T> *__restrict__ in, cplx<T> *__restrict__ ws, int w, T beta,
+                                                double iota)
+{
+    __shared__ T ker[kSpreadBatch][3 * kWMax];
+    __shared__ T frac[kSpreadBatch][3];
+    __shared__ cplx<T> val[kSpreadBatch];
+    __shared__ int org[kSpreadBatch][3];
+    const int tid = threadIdx.x;
+    const int p = (int)find_segment(tprefix, npairs, blockIdx.x);
+    const PairDev &P = pairs[p];
+    const int64_t lt = (int64_t)blockIdx.x - tprefix[p];
+    const int tx = (int)(lt % P.ntile[0]);
+    const int ty = (int)((lt / P.ntile[0]) % P.ntile[1]);
+    const int tz = (int)(lt / ((int64_t)P.ntile[0] * P.ntile[1]));
+    const int ox = tx * kTileX, oy = ty * kTileY, oz = tz * kTileZ;
+    const int x = tid % kTileX, y = tid / kTileX;
+    const int64_t gtile = P.tile0 + lt;
+    const int64_t r0 = toff[gtile], r1 = toff[gtile + 1];
     const T two_over_w = T(2) / T(w);
-    for (int64_t base = (int64_t)blockIdx.x * kWavesPerBlock; base < total;
-         base += (int64_t)gridDim.x * kWavesPerBlock) {
-        const int64_t g = base + wv;
-        const bool active = g < total;
-        int p = 0;
-        int l0[3] = {0, 0, 0};
-        cplx<T> cval = mk<T>(T(0), T(0));
-        if (active) {
-            p = (int)find_segment(prefix, npairs, g);
-            const PairDev &P = pairs[p];
-            const int64_t n = P.src_off + (g - prefix[p]);
+    T accr[kTileZ], acci[kTileZ];
+#pragma unroll
+    for (int z = 0; z < kTileZ; ++z) accr[z] = acci[z] = T(0);
+
+    for (int64_t base = r0; base < r1; base += kSpreadBatch) {
+        const int cnt = (int)min((int64_t)kSpreadBatch, r1 - base);
+        __syncthreads();
+        if (tid < cnt) {
+            const int64_t n = records[base + tid];
             double xp[3], t[3];
+            int c0[3];
+            source_footprint(P, xyz, nsrc, n, w, xp, t, c0);
             double ph = 0.0;
             for (int d = 0; d < 3; ++d) {
-                xp[d] = xyz[d * nsrc + n] - P.xc[d];
-                t[d] = xp[d] * P.kscale[d];
                 ph += P.sc[d] * xp[d];
+                frac[tid][d] = T((double)(c0[d] - P.n1[d] / 2) - t[d]);
             }
-            double2 e = cis_cycles(ph, iota);
-            cplx<T> c = in[perm[n]];
-            cval = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
-            for (int d = 0; d < 3; ++d) l0[d] = (int)ceil(t[d] - 0.5 * w);
-            if (lane < 3 * w) {
-                int d = lane / w, q = lane - d * w;
-                T off = T((double)(l0[d] + q) - t[d]);
-                ker[wv][lane] = es_kernel(off * two_over_w, beta);
-            }
+            org[tid][0] = c0[0] - ox;
+            org[tid][1] = c0[1] - oy;
+            org[tid][2] = c0[2] - oz;
+            const double2 e = cis_cycles(ph, iota);
+            const cplx<T> c = in[perm[n]];
+            val[tid] = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
         }
         __syncthreads();
-        if (active) {
-            const PairDev &P = pairs[p];
-            const int n1x = P.n1[0], n1y = P.n1[1], n1z = P.n1[2];
-            const int ix0 = l0[0] + n1x / 2, iy0 = l0[1] + n1y / 2, iz0 = l0[2] + n1z / 2;
-            T *grid = reinterpret_cast<T *>(ws + P.bufA);
-            for (int e = lane; e < w * w; e += 64) {
-                const int dy = e / w, dx = e - dy * w;
-                const int ix = ix0 + dx, iy = iy0 + dy;
-                if (ix < 0 || ix >= n1x || iy < 0 || iy >= n1y) continue;
-                const T kxy = ker[wv][dx] * ker[wv][w + dy];
-                const cplx<T> v = cscale<T>(cval, kxy);
-                for (int dz = 0; dz < w; ++dz) {
-                    const int iz = iz0 + dz;
-                    if (iz < 0 || iz >= n1z) continue;
-                    const T kz = ker[wv][2 * w + dz];
-                    const int64_t idx = ((int64_t)iz * n1y + iy) * n1x + ix;
-                    atomicAdd(grid + 2 * idx, v.x * kz);
-                    atomicAdd(grid + 2 * idx + 1, v.y * kz);
+        for (int i = tid; i < cnt * 3 * w; i += 256) {
+            const int j = i / (3 * w), r = i - j * 3 * w, d = r / w, q = r - d * w;
+            ker[j][r] = es_kernel((frac[j][d] + T(q)) * two_over_w, beta);
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            const int qx = x - org[j][0], qy = y - org[j][1];
+            if ((unsigned)qx >= (unsigned)w || (unsigned)qy >= (unsigned)w) continue;
+            const T kxy = ker[j][qx] * ker[j][w + qy];
+            const T vr = val[j].x * kxy, vi = val[j].y * kxy;
+            const int oz0 = org[j][2];
+#pragma unroll
+            for (int z = 0; z < kTileZ; ++z) {
+                const int qz = z - oz0;
+                if ((unsigned)qz < (unsigned)w) {
+                    const T kz = ker[j][2 * w + qz];
+                    accr[z] += vr * kz;
+                    acci[z] += vi * kz;
                 }
             }
         }
-        __syncthreads();
+    }
+    const int gx = ox + x, gy = oy + y;
+    if (gx < P.n1[0] && gy < P.n1[1]) {
+        cplx<T> *grid = ws + P.bufA;
+#pragma unroll
+        for (int z = 0; z < kTileZ; ++z) {
+            const int gz = oz + z;
+            if (gz < P.n1[2]) grid[((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx] = mk<T>(accr[z], acci[z]);
+        }
     }
 }
 
@@ -547,15 +620,25 @@ hipError_t launch_deconv(const double *xyz, int64_t n, const int32_t *chunk_of, 
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_spread(const PairDev *pairs, const int64_t *prefix, int npairs, int64_t total, const double *xyz,
-                         int64_t nsrc, const int32_t *perm, const void *in, void *ws, int w, double beta, double iota,
-                         hipStream_t st)
+hipError_t launch_bin(const PairDev *pairs, const int64_t *prefix, int npairs, int64_t total, const double *xyz,
+                      int64_t nsrc, int w, int32_t *counts, unsigned long long *cursor, int32_t *records,
+                      hipStream_t st)
 {
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spread<T>, dim3(blocks_for(total, kWavesPerBlock, 1 << 16)), dim3(256), 0, st, pairs,
-                       prefix, npairs, total, xyz, nsrc, perm, static_cast<const cplx<T> *>(in),
-                       static_cast<cplx<T> *>(ws), w, T(beta), iota);
+    hipLaunchKernelGGL(k_bin_points, dim3(blocks_for(total, 256, INT32_MAX)), dim3(256), 0, st, pairs, prefix, npairs,
+                       total, xyz, nsrc, w, counts, cursor, records);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spread(const PairDev *pairs, const int64_t *tprefix, int npairs, int64_t tiles, const int64_t *toff,
+                         const int32_t *records, const double *xyz, int64_t nsrc, const int32_t *perm, const void *in,
+                         void *ws, int w, double beta, double iota, hipStream_t st)
+{
+    if (tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spread<T>, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, st, pairs, tprefix, npairs,
+                       toff, records, xyz, nsrc, perm, static_cast<const cplx<T> *>(in), static_cast<cplx<T> *>(ws), w,
+                       T(beta), iota);
     return hipGetLastError();
 }
 
@@ -603,10 +686,12 @@ hipError_t launch_finalize(const double *acc, int64_t n, const int32_t *perm, vo
     return hipGetLastError();
 }
 
-template hipError_t launch_spread<float>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
-                                         const int32_t *, const void *, void *, int, double, double, hipStream_t);
-template hipError_t launch_spread<double>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
-                                          const int32_t *, const void *, void *, int, double, double, hipStream_t);
+template hipError_t launch_spread<float>(const PairDev *, const int64_t *, int, int64_t, const int64_t *,
+                                         const int32_t *, const double *, int64_t, const int32_t *, const void *,
+                                         void *, int, double, double, hipStream_t);
+template hipError_t launch_spread<double>(const PairDev *, const int64_t *, int, int64_t, const int64_t *,
+                                          const int32_t *, const double *, int64_t, const int32_t *, const void *,
+                                          void *, int, double, double, hipStream_t);
 template hipError_t launch_fft<float>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,
                                       const double *, int, double, hipStream_t);
 template hipError_t launch_fft<double>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,

@@ -58,6 +58,34 @@ int es_params(double eps, double sigma, int *w, double *beta)
     return HVOX_OK;
 }
 
+// Upsampling factors and kernels for a per-sub-problem accuracy eps_sub.
+// Both type-3 stages divide by a kernel transform that falls by
+// ~exp(-c(sigma) beta) per dimension towards the edge of its band
+// (c = 0.27 at sigma = 1.25, 0.14 at 1.5): targets near the corners of a box
+// populated in all three dimensions, and the inner FFT's edge modes, are then
+// recovered from sums that cancel by that factor cubed, which costs digits of
+// the working precision as beta (i.e. w) grows.  Measured on chunked 3D
+// sub-problems: the inner stage stays within eps at sigma2 = 1.5 for every
+// supported eps; spreading at sigma = 1.25 stays within eps while w <= 8
+// (float32) or w <= 12 (float64), and sigma = 1.5 is used beyond.
+int choose_kernels(Params *p, double eps_sub)
+{
+    const double e = std::min(eps_sub, 0.5);
+    p->sigma2 = p->sigma2_opt > 0.0 ? p->sigma2_opt : 1.5;
+    int rc = es_params(e, p->sigma2, &p->w2, &p->beta2);
+    if (rc) return rc;
+    if (p->sigma_opt > 0.0) {
+        p->sigma = p->sigma_opt;
+        return es_params(e, p->sigma, &p->w, &p->beta);
+    }
+    const int wmax_125 = p->dtype == HVOX_F64 ? 12 : 8;
+    p->sigma = 1.25;
+    rc = es_params(e, p->sigma, &p->w, &p->beta);
+    if (rc == HVOX_OK && p->w <= wmax_125) return HVOX_OK;
+    p->sigma = 1.5;
+    return es_params(e, p->sigma, &p->w, &p->beta);
+}
+
 // Smallest even n' >= n whose prime factors are 2, 3 and 5 only.
 int32_t smooth_even(int64_t n)
 {
@@ -439,7 +467,7 @@ double pair_nufft_seconds(const PairGeom &g, int64_t ns, int64_t nt, const Param
 {
     const Rates r = rates_for(p.dtype);
     const double delta = p.dtype == HVOX_F64 ? 16.0 : 8.0;
-    double b = delta * (static_cast<double>(g.bufA) + g.g1 + 2.0 * g.bx + 2.0 * g.cy + g.dz);
+    double b = delta * (static_cast<double>(g.g1) + g.g1 + 2.0 * g.bx + 2.0 * g.cy + g.dz);
     if (bytes) *bytes = b;
     const double w3 = static_cast<double>(p.w) * p.w * p.w, w23 = static_cast<double>(p.w2) * p.w2 * p.w2;
     return b / r.hbm_bytes_per_s + (ns * w3 + nt * w23) / r.cells_per_s + r.pair_overhead_s;
@@ -505,6 +533,8 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
     dp->batches.clear();
     dp->pre_pts.clear();
     dp->pre_tgts.clear();
+    dp->pre_stiles.clear();
+    dp->tiles_total = 0;
     for (int q = 0; q < 3; ++q) dp->pre_tiles[q].clear();
     const int64_t cap = static_cast<int64_t>(hp.ws_elems);
     size_t k = 0;
@@ -523,13 +553,13 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
         b.npairs = static_cast<int64_t>(k1 - k);
         b.pre_pts = static_cast<int64_t>(dp->pre_pts.size());
         b.pre_tgts = static_cast<int64_t>(dp->pre_tgts.size());
+        b.pre_stiles = static_cast<int64_t>(dp->pre_stiles.size());
+        dp->pre_stiles.push_back(0);
         for (int q = 0; q < 3; ++q) b.pre_tiles[q] = static_cast<int64_t>(dp->pre_tiles[q].size());
         dp->pre_pts.push_back(0);
         dp->pre_tgts.push_back(0);
         for (int q = 0; q < 3; ++q) dp->pre_tiles[q].push_back(0);
-        int64_t offA = 0, offB = sumA;
-        b.zero_off = 0;
-        b.zero_cnt = sumA;
+        int64_t offA = 0, offB = sumA;   // all grid-1 (A) buffers first, then the B buffers
         for (size_t m = k; m < k1; ++m) {
             const Cand &c = nufft[m];
             const PairGeom &g = c.g;
@@ -562,6 +592,14 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
             }
             pd.bufA = offA;
             pd.bufB = offB;
+            pd.ntile[0] = (g.n1[0] + kTileX - 1) / kTileX;
+            pd.ntile[1] = (g.n1[1] + kTileY - 1) / kTileY;
+            pd.ntile[2] = (g.n1[2] + kTileZ - 1) / kTileZ;
+            const int64_t nst = static_cast<int64_t>(pd.ntile[0]) * pd.ntile[1] * pd.ntile[2];
+            pd.tile0 = dp->tiles_total;
+            dp->tiles_total += nst;
+            b.stiles += nst;
+            dp->pre_stiles.push_back(dp->pre_stiles.back() + nst);
             offA += g.bufA;
             offB += g.bufB;
             int64_t lines[3] = {static_cast<int64_t>(g.n1[2]) * g.n1[1],
@@ -581,9 +619,9 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
             dp->pre_tgts.push_back(dp->pre_tgts.back() + pd.tgt_cnt);
             dp->grid_cells += static_cast<double>(g.g1);
             // algorithmic HBM bytes per kernel (see the kernel documentation)
-            dp->alg_bytes[HVOX_K_ZERO] += delta * g.bufA;
-            dp->alg_bytes[HVOX_K_SPREAD] += pd.src_cnt * (24.0 + 4.0 + delta) +
-                                            delta * std::min(static_cast<double>(g.g1), pd.src_cnt * w3);
+            // spreading writes every grid-1 cell once and reads each source
+            // (coordinates, permutation, value, tile record) per tile it touches
+            dp->alg_bytes[HVOX_K_SPREAD] += pd.src_cnt * (24.0 + 4.0 + 4.0 + delta) + delta * static_cast<double>(g.g1);
             dp->alg_bytes[HVOX_K_FFT_X] += delta * (static_cast<double>(g.g1) + g.bx);
             dp->alg_bytes[HVOX_K_FFT_Y] += delta * (static_cast<double>(g.bx) + g.cy);
             dp->alg_bytes[HVOX_K_FFT_Z] += delta * (static_cast<double>(g.cy) + g.dz);
@@ -629,48 +667,69 @@ int make_host_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t 
     }
     floor_widths(Bw, Pw, p.sigma);
 
-    // Algorithm 1 with the budget expressed as a Heisenberg volume: the two
-    // grid buffers of a sub-problem hold ~ 2 prod(sigma h eta) cells of delta
-    // bytes.  The padded sizes (kernel support, smooth FFT lengths, output
-    // window) are then checked on a lattice-sized sub-problem and the
-    // volume is reduced until they fit the budget and the LDS FFT length.
-    const double budget = p.max_fft_bytes;
-    double vmax = std::isfinite(budget) ? budget / (2.0 * p.sigma * p.sigma * p.sigma * delta) : INFINITY;
-    int rc = HVOX_OK;
-    for (int it = 0; it < 200; ++it) {
-        rc = alg1(Bw, Pw, vmax, p.alpha, hp->h, hp->eta);
-        if (rc != HVOX_OK) { *err = "Algorithm 1 rejected its inputs"; return rc; }
-        double X[3], S[3];
-        for (int d = 0; d < 3; ++d) { X[d] = 0.5 * hp->eta[d]; S[d] = 0.5 * hp->h[d]; }
-        PairGeom g = pair_geometry(X, S, p);
-        bool ok = g.fits && (!std::isfinite(budget) || ws_of(g) * delta <= budget);
-        if (ok) break;
-        double shrink = 0.7;
-        if (g.fits && std::isfinite(budget)) shrink = std::min(0.9, std::max(0.3, budget / (ws_of(g) * delta)));
-        double cur = 1.0;
-        for (int d = 0; d < 3; ++d) cur *= hp->h[d] * hp->eta[d];
-        double floor_v = 1.0;
-        for (int d = 0; d < 3; ++d) floor_v *= std::min(1.0, Bw[d] * Pw[d]) / p.sigma;
-        if (cur * shrink < floor_v) break;      // padding alone exceeds the budget: smallest boxes
-        vmax = cur * shrink;
-    }
+    // Algorithm 1 + Algorithm 2 for the current kernel widths.
+    auto partition_domains = [&]() -> int {
+        // Algorithm 1 with the budget expressed as a Heisenberg volume: the two
+        // grid buffers of a sub-problem hold ~ 2 prod(sigma h eta) cells of delta
+        // bytes.  The padded sizes (kernel support, smooth FFT lengths, output
+        // window) are then checked on a lattice-sized sub-problem and the
+        // volume is reduced until they fit the budget and the LDS FFT length.
+        const double budget = p.max_fft_bytes;
+        double vmax = std::isfinite(budget) ? budget / (2.0 * p.sigma * p.sigma * p.sigma * delta) : INFINITY;
+        int rc = HVOX_OK;
+        for (int it = 0; it < 200; ++it) {
+            rc = alg1(Bw, Pw, vmax, p.alpha, hp->h, hp->eta);
+            if (rc != HVOX_OK) { *err = "Algorithm 1 rejected its inputs"; return rc; }
+            double X[3], S[3];
+            for (int d = 0; d < 3; ++d) { X[d] = 0.5 * hp->eta[d]; S[d] = 0.5 * hp->h[d]; }
+            PairGeom g = pair_geometry(X, S, p);
+            bool ok = g.fits && (!std::isfinite(budget) || ws_of(g) * delta <= budget);
+            if (ok) break;
+            double shrink = 0.7;
+            if (g.fits && std::isfinite(budget)) shrink = std::min(0.9, std::max(0.3, budget / (ws_of(g) * delta)));
+            double cur = 1.0;
+            for (int d = 0; d < 3; ++d) cur *= hp->h[d] * hp->eta[d];
+            double floor_v = 1.0;
+            for (int d = 0; d < 3; ++d) floor_v *= std::min(1.0, Bw[d] * Pw[d]) / p.sigma;
+            if (cur * shrink < floor_v) break;      // padding alone exceeds the budget: smallest boxes
+            vmax = cur * shrink;
+        }
 
-    // Algorithm 2 on both domains (or the caller's partitions)
-    std::vector<int32_t> lv(n_vis), ls(n_pix);
-    if (vis_chunk) std::copy(vis_chunk, vis_chunk + n_vis, lv.begin());
-    else if (n_vis > 0) {
-        int64_t nc = partition(uvw, n_vis, hp->h, lv.data());
-        if (nc < 0) { *err = "Algorithm 2 failed on the visibilities"; return static_cast<int>(nc); }
-    }
-    if (sky_chunk) std::copy(sky_chunk, sky_chunk + n_pix, ls.begin());
-    else if (n_pix > 0) {
-        int64_t nc = partition(xyz, n_pix, hp->eta, ls.data());
-        if (nc < 0) { *err = "Algorithm 2 failed on the sky"; return static_cast<int>(nc); }
-    }
-    rc = build_chunkset(uvw, n_vis, lv.data(), &hp->vis, err);
+        // Algorithm 2 on both domains (or the caller's partitions)
+        std::vector<int32_t> lv(n_vis), ls(n_pix);
+        if (vis_chunk) std::copy(vis_chunk, vis_chunk + n_vis, lv.begin());
+        else if (n_vis > 0) {
+            int64_t nc = partition(uvw, n_vis, hp->h, lv.data());
+            if (nc < 0) { *err = "Algorithm 2 failed on the visibilities"; return static_cast<int>(nc); }
+        }
+        if (sky_chunk) std::copy(sky_chunk, sky_chunk + n_pix, ls.begin());
+        else if (n_pix > 0) {
+            int64_t nc = partition(xyz, n_pix, hp->eta, ls.data());
+            if (nc < 0) { *err = "Algorithm 2 failed on the sky"; return static_cast<int>(nc); }
+        }
+        rc = build_chunkset(uvw, n_vis, lv.data(), &hp->vis, err);
+        if (rc) return rc;
+        rc = build_chunkset(xyz, n_pix, ls.data(), &hp->sky, err);
+        if (rc) return rc;
+        return HVOX_OK;
+    };
+    int rc = partition_domains();
     if (rc) return rc;
-    rc = build_chunkset(xyz, n_pix, ls.data(), &hp->sky, err);
-    if (rc) return rc;
+    // Chunked evaluation sums K > 1 sub-problems into every output; their
+    // errors add up (the paper notes the chunked result slightly misses eps
+    // and suggests a smaller eps per sub-transform).  Reading: the kernels are
+    // sized for eps / min(4, K), then the partition is recomputed with them.
+    const int32_t K = std::max(hp->vis.nc, hp->sky.nc);
+    if (K > 1 && !p.all_direct && p.eps > 0.0) {
+        const double eps_sub = p.eps / std::min(4, K);
+        if (choose_kernels(&p, eps_sub) != HVOX_OK) {
+            *err = "no kernel for the per-sub-problem accuracy";
+            return HVOX_ERR_EPS;
+        }
+        p.eps_sub = eps_sub;
+        rc = partition_domains();
+        if (rc) return rc;
+    }
 
     // effective target half-widths: a dimension narrower than half a grid
     // cell against every source chunk is floored (its phase is negligible)

@@ -53,6 +53,7 @@ class HvoxPlanInfo(ctypes.Structure):
                 ("beta", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("w2", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("beta2", ctypes.c_double), ("sigma2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("eps_sub", ctypes.c_double),
                 ("h", ctypes.c_double * 3), ("eta", ctypes.c_double * 3),
                 ("n_vis_chunks", ctypes.c_int32), ("n_sky_chunks", ctypes.c_int32),
                 ("n_pairs_nufft", ctypes.c_int64), ("n_pairs_direct", ctypes.c_int64),

@@ -107,7 +107,9 @@ def test_host_plan_compact_disk_monolithic():
     inf = p.info()
     assert inf["n_vis_chunks"] == 1 and inf["n_sky_chunks"] == 1
     assert inf["n_pairs_nufft"] == 1 and inf["n_pairs_direct"] == 0
-    assert inf["w"] == 11
+    # one chunk: kernels for eps itself; spreading at sigma = 1.25 (w = 11 <= 12), inner FFT at sigma2 = 1.5
+    assert inf["sigma"] == 1.25 and inf["w"] == 11 and inf["sigma2"] == 1.5 and inf["w2"] == 9
+    assert inf["eps_sub"] == 1e-6
     vp, sp = p.permutation()
     assert sorted(vp) == list(range(wl.n_vis)) and sorted(sp) == list(range(wl.n_pix))
     with pytest.raises(hv.HvoxError):
