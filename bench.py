@@ -113,10 +113,12 @@ def roofline_entry(st, dtype):
 
 # VALU instructions issued per (target, source) term by the direct kernel's
 # inner loop, counted from its gfx950 assembly (LDS reads and scalar loop
-# control excluded): float32 plan 15 (float64 dot, reduction, conversion,
-# hardware sine and cosine, complex multiply-accumulate); float64 plan 60
-# (the float64 sincospi dominates).  Each is one lane-operation per lane.
-VALU_OPS_PER_TERM = {"f32": 15.0, "f64": 60.0}
+# control excluded): float32 plan 45 per 4-term unrolled iteration (float64
+# dot and fractional part, conversion, hardware sine and cosine, complex
+# multiply-accumulate); float64 plan 86 per 2-term iteration (float64 dot,
+# quarter-turn reduction, Maclaurin sine and cosine, rotation, complex
+# multiply-accumulate).  Each is one lane-operation per lane.
+VALU_OPS_PER_TERM = {"f32": 45.0 / 4.0, "f64": 86.0 / 2.0}
 
 
 def cpu_baseline(wl, target_s=12.0):

@@ -129,7 +129,8 @@ typedef struct {
 #define HVOX_K_INTERP   5
 #define HVOX_K_DIRECT   6
 #define HVOX_K_FINAL    7
-#define HVOX_K_COUNT    8
+#define HVOX_K_TRANSPOSE 8
+#define HVOX_K_COUNT    9
 typedef struct {
     int64_t launches[HVOX_K_COUNT];
     double  ms[HVOX_K_COUNT];           /* summed HIP-event durations */

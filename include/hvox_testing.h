@@ -16,14 +16,14 @@ extern "C" {
 /*
  * One pass of the library's LDS-resident mixed-radix FFT (the kernel of the
  * type-3 transform's FFT step, HVOX Sect. 3) on `nlines` lines:
- *   out[q][j] = sum_{e < nin} in[j][e] exp(sign 2 pi i (e - nin/2) m_q / n),
+ *   out[j][q] = sum_{e < nin} in[j][e] exp(sign 2 pi i (e - nin/2) m_q / n),
  *   m_q = (wstart + q) mod n,  q < wcount,
  * i.e. modes -nin/2 .. nin/2-1 zero-padded to an n-point FFT, of which the
  * window of wcount outputs starting at index wstart (may be negative) is
- * kept, written transposed.  n must be even, 2-3-5 smooth and <= 4096,
+ * kept, written line by line.  n must be even, 2-3-5 smooth and <= 4096,
  * nin even and <= n, wcount <= n, sign = -1 or +1.
  * dtype HVOX_F32 (complex64) or HVOX_F64 (complex128); in and out are device
- * buffers of nlines*nin and wcount*nlines complex values.  Work is enqueued
+ * buffers of nlines*nin and nlines*wcount complex values.  Work is enqueued
  * on stream; the call returns after synchronising it.
  */
 int hvox_test_fft(int32_t dtype, int32_t n, int32_t nin, int32_t nlines, int32_t wstart, int32_t wcount,

@@ -30,6 +30,8 @@ template <typename T>
 hipError_t launch_fft(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *, const double *, int,
                       double, hipStream_t);
 template <typename T>
+hipError_t launch_transpose(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
+template <typename T>
 hipError_t launch_interp(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t, const double *,
                          const void *, double *, int, double, double, hipStream_t);
 template <typename T>
@@ -54,6 +56,7 @@ struct DevDir {
     DirectItem *direct = nullptr;
     double *deconv = nullptr;        // per chunk-order target
     int64_t *pre_stiles = nullptr;   // per batch: tile prefix over its pairs
+    int64_t *pre_ttiles = nullptr;   // per batch: transpose-tile prefix over its pairs
     int64_t *tile_off = nullptr;     // [tiles_total + 1] record offsets of every grid-1 tile
     int32_t *records = nullptr;      // source indices listed per tile (plan-resident binning)
 };
@@ -222,11 +225,16 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
                 return launch_spread<T>(pairs, dd.pre_stiles + b.pre_stiles, np, b.stiles, dd.tile_off, dd.records,
                                         sxyz, n_src, sperm, in_t, pl->ws, p.w, p.beta, iota, st);
             }));
-            for (int pass = 0; pass < 3; ++pass)
+            for (int pass = 0; pass < 3; ++pass) {
                 HVOX_TRY(timed(pl, HVOX_K_FFT_X + pass, st, [&] {
                     return launch_fft<T>(pairs, dd.pre_tiles[pass] + b.pre_tiles[pass], np, b.tiles[pass], pass,
                                          pl->ws, pl->tw, pl->precor, b.lds_elems[pass], iota, st);
                 }));
+                if (pass == 0)
+                    HVOX_TRY(timed(pl, HVOX_K_TRANSPOSE, st, [&] {
+                        return launch_transpose<T>(pairs, dd.pre_ttiles + b.pre_ttiles, np, b.ttiles, pl->ws, st);
+                    }));
+            }
             HVOX_TRY(timed(pl, HVOX_K_INTERP, st, [&] {
                 return launch_interp<T>(pairs, dd.pre_tgts + b.pre_tgts, np, b.tgts, txyz, n_tgt, dd.deconv, pl->ws,
                                         pl->acc, p.w2, p.beta2, iota, st);
@@ -276,6 +284,7 @@ int upload_dir(hvox_plan_s *pl, const DirPlan &dp, DevDir *dd, hipStream_t st)
         if ((e = upload(pl, dp.pre_tiles[q], &dd->pre_tiles[q], st)) != hipSuccess) return HVOX_ERR_OOM;
     if ((e = upload(pl, dp.direct, &dd->direct, st)) != hipSuccess) return HVOX_ERR_OOM;
     if ((e = upload(pl, dp.pre_stiles, &dd->pre_stiles, st)) != hipSuccess) return HVOX_ERR_OOM;
+    if ((e = upload(pl, dp.pre_ttiles, &dd->pre_ttiles, st)) != hipSuccess) return HVOX_ERR_OOM;
     return HVOX_OK;
 }
 

@@ -12,7 +12,8 @@ namespace hvox {
 
 // ---- compile-time limits -------------------------------------------------
 constexpr int kWMax = 24;            // largest kernel support handled by the kernels
-constexpr int kFftThreads = 256;     // threads of one FFT workgroup
+constexpr int kFftThreads = 512;     // threads of one FFT workgroup
+constexpr int kTransposeTile = 32;   // square tile of the transpose kernel
 constexpr int kFftElems = 4096;      // complex elements (lines x length) held in LDS by one workgroup
 constexpr int kFftMaxLen = 4096;     // longest 1D FFT (one line must fit a workgroup)
 constexpr int kFftMaxLines = 64;     // lines per FFT workgroup
@@ -27,6 +28,10 @@ constexpr int kTileX = 32, kTileY = 8, kTileZ = 8;
 constexpr int kSpreadBatch = 64;
 
 // ---- one type-3 sub-problem (source chunk -> target chunk) on the device ---
+// FFT passes: x reads grid 1 (contiguous lines) and writes its kept window
+// line-major; a tiled transpose makes the y lines contiguous; y writes
+// line-major; z reads its (short) lines strided, consecutive lines in
+// adjacent lanes, and writes line-major, leaving a z-fastest grid.
 // Sub-problem math (Sect. 3, the four type-3 steps; centring as in the
 // published type-3 method the paper builds on):
 //   f_k = e^{2 pi i iota s_k.x_c} sum_n [c_n e^{2 pi i iota s_c.x'_n}] e^{2 pi i iota s'_k.x'_n}
@@ -47,7 +52,10 @@ struct PairDev {
     int32_t wcount[3];           // kept FFT outputs per dimension
     int32_t nrad[3];             // radix stages per dimension
     int32_t lines_per_tile[3];   // FFT lines per workgroup, per pass
-    int64_t bufA, bufB;          // complex-element offsets of the two grid buffers in the workspace
+    int64_t bufA, bufB;          // complex-element offsets of the two grid buffers in the workspace:
+                                 //   A: grid 1 [n1z][n1y][n1x] -> x-pass output transposed [n1z][wx][n1y]
+                                 //      -> z-pass output [wx][wy][wz] (read by the interpolation)
+                                 //   B: x-pass output [n1z][n1y][wx] -> y-pass output [n1z][wx][wy]
     int64_t tile0;               // index of the pair's first grid-1 tile among the direction's tiles
     int32_t ntile[3];            // grid-1 tiles per dimension
     int32_t pad_;
@@ -81,6 +89,8 @@ struct Batch {
     int64_t tiles[3] = {0, 0, 0};        // FFT workgroups per pass
     int64_t stiles = 0;                  // spreading tiles (workgroups)
     int64_t pre_stiles = 0;              // offset of the batch's tile prefix array
+    int64_t ttiles = 0;                  // transpose tiles (workgroups)
+    int64_t pre_ttiles = 0;              // offset of the batch's transpose-tile prefix array
     int64_t ws_end = 0;                  // end of the batch's workspace use (complex elements)
     int64_t pre_pts = 0, pre_tgts = 0;   // offsets into the prefix arrays
     int64_t pre_tiles[3] = {0, 0, 0};
@@ -93,6 +103,7 @@ struct DirPlan {                         // one direction (synthesis or analysis
     std::vector<Batch> batches;
     std::vector<int64_t> pre_pts, pre_tgts, pre_tiles[3];   // per batch: npairs+1 prefix sums
     std::vector<int64_t> pre_stiles;     // per batch: npairs+1 prefix sums of spreading tiles
+    std::vector<int64_t> pre_ttiles;     // per batch: npairs+1 prefix sums of transpose tiles
     int64_t tiles_total = 0;             // spreading tiles over all batches
     std::vector<DirectItem> direct;
     double grid_cells = 0.0, direct_terms = 0.0;

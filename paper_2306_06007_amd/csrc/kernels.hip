@@ -338,12 +338,14 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int p, const cplx<T> *__r
     __syncthreads();
 }
 
-// One axis pass for every sub-problem of a batch.  Lines of the pass input
-// are contiguous ([lines][nin]); element e of a line is mode l = e - nin/2,
-// placed at FFT slot l mod n (zero elsewhere: the zero padding of grid 1 into
-// grid 2 is never stored).  The x pass also applies the separable
-// pre-correction 1/Phi_hat(l/n2) of all three axes.  Output q of the kept
-// window is FFT index (wstart + q) mod n, written to out[q][line].
+// One axis pass for every sub-problem of a batch.  Element e of an input
+// line is mode l = e - nin/2, placed at FFT slot l mod n (zero elsewhere: the
+// zero padding of grid 1 into grid 2 is never stored).  The x and y passes
+// read contiguous lines; the z pass reads its lines strided (line j of the
+// plane is element j of every z-slab, so consecutive lines sit in adjacent
+// lanes).  The x pass also applies the separable pre-correction
+// 1/Phi_hat(l/n2) of all three axes.  Output q of the kept window is FFT index
+// (wstart + q) mod n, written line-major: out[line][q].
 template <typename T>
 __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restrict__ pairs,
                                                           const int64_t *__restrict__ prefix, int npairs, int pass,
@@ -361,28 +363,38 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restr
     const cplx<T> *src;
     cplx<T> *dst;
     if (pass == 0) { lines = (int64_t)P.n1[2] * P.n1[1]; src = ws + P.bufA; dst = ws + P.bufB; }
-    else if (pass == 1) { lines = (int64_t)P.wcount[0] * P.n1[2]; src = ws + P.bufB; dst = ws + P.bufA; }
-    else { lines = (int64_t)P.wcount[1] * P.wcount[0]; src = ws + P.bufA; dst = ws + P.bufB; }
+    else if (pass == 1) { lines = (int64_t)P.n1[2] * P.wcount[0]; src = ws + P.bufA; dst = ws + P.bufB; }
+    else { lines = (int64_t)P.wcount[0] * P.wcount[1]; src = ws + P.bufB; dst = ws + P.bufA; }
     const int L = P.lines_per_tile[pass];
     const int64_t line0 = tile * L;
     const int nl = (int)min((int64_t)L, lines - line0);
     const int half_in = nin / 2;
 
-    for (int e = threadIdx.x; e < nl * n; e += kFftThreads) {
-        const int j = e / n, f = e - j * n;
-        const int l = f < n / 2 ? f : f - n;
-        cplx<T> v = mk<T>(T(0), T(0));
-        if (l >= -half_in && l < half_in) {
-            const int64_t li = line0 + j;
-            v = src[li * nin + (l + half_in)];
-            if (pass == 0) {
-                const int64_t lz = li / P.n1[1], ly = li - lz * P.n1[1];
-                const double fac = precor[P.precor[0] + l + half_in] * precor[P.precor[1] + ly] *
-                                   precor[P.precor[2] + lz];
-                v = cscale<T>(v, T(fac));
+    if (pass < 2) {
+        for (int e = threadIdx.x; e < nl * n; e += kFftThreads) {
+            const int j = e / n, f = e - j * n;
+            const int l = f < n / 2 ? f : f - n;
+            cplx<T> v = mk<T>(T(0), T(0));
+            if (l >= -half_in && l < half_in) {
+                const int64_t li = line0 + j;
+                v = src[li * nin + (l + half_in)];
+                if (pass == 0) {
+                    const int64_t lz = li / P.n1[1], ly = li - lz * P.n1[1];
+                    const double fac = precor[P.precor[0] + l + half_in] * precor[P.precor[1] + ly] *
+                                       precor[P.precor[2] + lz];
+                    v = cscale<T>(v, T(fac));
+                }
             }
+            lds[j * n + f] = v;
         }
-        lds[j * n + f] = v;
+    } else {
+        for (int e = threadIdx.x; e < nl * n; e += kFftThreads) {
+            const int f = e / nl, j = e - f * nl;
+            const int l = f < n / 2 ? f : f - n;
+            cplx<T> v = mk<T>(T(0), T(0));
+            if (l >= -half_in && l < half_in) v = src[(int64_t)(l + half_in) * lines + line0 + j];
+            lds[j * n + f] = v;
+        }
     }
     __syncthreads();
     const cplx<T> *tw = twtab + P.tw[pass];
@@ -395,19 +407,52 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restr
         else fft_stage<T, 5>(lds, nl, n, pc, tw, s);
         pc *= R;
     }
+    cplx<T> *out = dst + line0 * wcnt;
     for (int e = threadIdx.x; e < nl * wcnt; e += kFftThreads) {
-        const int q = e / nl, j = e - q * nl;
+        const int j = e / wcnt, q = e - j * wcnt;
         int m = (wst + q) % n;
         if (m < 0) m += n;
-        dst[(int64_t)q * lines + line0 + j] = lds[j * n + m];
+        out[e] = lds[j * n + m];
+    }
+}
+
+// Transpose of the x-pass output for the y pass: per z-slab, B[y][x'] ->
+// A[x'][y], through a padded LDS tile so reads and writes are both coalesced.
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(const PairDev *__restrict__ pairs, const int64_t *__restrict__ prefix,
+                                                   int npairs, cplx<T> *__restrict__ ws)
+{
+    __shared__ cplx<T> tile[kTransposeTile][kTransposeTile + 1];
+    const int p = (int)find_segment(prefix, npairs, blockIdx.x);
+    const PairDev &P = pairs[p];
+    const int64_t local = (int64_t)blockIdx.x - prefix[p];
+    const int R = P.n1[1], C = P.wcount[0];
+    const int tr = (R + kTransposeTile - 1) / kTransposeTile, tc = (C + kTransposeTile - 1) / kTransposeTile;
+    const int64_t z = local / ((int64_t)tr * tc);
+    const int rem = (int)(local - z * tr * tc);
+    const int ti = rem / tc, tj = rem - ti * tc;
+    const cplx<T> *in = ws + P.bufB + z * (int64_t)R * C;
+    cplx<T> *out = ws + P.bufA + z * (int64_t)R * C;
+    const int tx = threadIdx.x % kTransposeTile, ty = threadIdx.x / kTransposeTile;
+    constexpr int rows_per_pass = 256 / kTransposeTile;
+#pragma unroll
+    for (int k = 0; k < kTransposeTile; k += rows_per_pass) {
+        const int r = ti * kTransposeTile + ty + k, c = tj * kTransposeTile + tx;
+        if (r < R && c < C) tile[ty + k][tx] = in[(int64_t)r * C + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTransposeTile; k += rows_per_pass) {
+        const int c = tj * kTransposeTile + ty + k, r = ti * kTransposeTile + tx;
+        if (r < R && c < C) out[(int64_t)c * R + r] = tile[tx][ty + k];
     }
 }
 
 // ---------------------------------------------------------------------------
 // interpolation + deconvolution + post-phase (type-3 steps 3-4):
 //   f_k += exp(2 pi i iota s_k.x_c) / prod Psi_hat(.) * sum_m G_m prod_d ES((m_d - tau_kd) 2/w)
-// One wavefront per target; lanes cover the (x, y) rows of its w^3 window,
-// loop over z, and reduce across the wavefront.  Accumulation is float64
+// One wavefront per target; lanes cover the (y, z) pairs of its w^3 window
+// (z fastest, as the grid), loop over x, and reduce across the wavefront.  Accumulation is float64
 // (cross-sub-problem sums stay in double precision).
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -448,26 +493,26 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
             const int wx = P.wcount[0], wy = P.wcount[1], wz = P.wcount[2];
             const int n2x = P.n2[0], n2y = P.n2[1], n2z = P.n2[2];
             const int sx = P.wstart[0], sy = P.wstart[1], sz = P.wstart[2];
-            const cplx<T> *grid = ws + P.bufB;
+            const cplx<T> *grid = ws + P.bufA;          // [wx][wy][wz], z fastest
             for (int e = lane; e < w * w; e += 64) {
-                const int dy = e / w, dx = e - dy * w;
-                int qx = m0[0] + dx - sx, qy = m0[1] + dy - sy;
-                if (wx == n2x) { qx %= n2x; if (qx < 0) qx += n2x; }
+                const int dy = e / w, dz = e - dy * w;
+                int qy = m0[1] + dy - sy, qz = m0[2] + dz - sz;
                 if (wy == n2y) { qy %= n2y; if (qy < 0) qy += n2y; }
-                if (qx < 0 || qx >= wx || qy < 0 || qy >= wy) continue;
-                const T kxy = ker[wv][dx] * ker[wv][w + dy];
+                if (wz == n2z) { qz %= n2z; if (qz < 0) qz += n2z; }
+                if (qy < 0 || qy >= wy || qz < 0 || qz >= wz) continue;
+                const T kyz = ker[wv][w + dy] * ker[wv][2 * w + dz];
                 T sr = T(0), si = T(0);
-                for (int dz = 0; dz < w; ++dz) {
-                    int qz = m0[2] + dz - sz;
-                    if (wz == n2z) { qz %= n2z; if (qz < 0) qz += n2z; }
-                    if (qz < 0 || qz >= wz) continue;
-                    const T kz = ker[wv][2 * w + dz];
-                    const cplx<T> gv = grid[((int64_t)qz * wy + qy) * wx + qx];
-                    sr += gv.x * kz;
-                    si += gv.y * kz;
+                for (int dx = 0; dx < w; ++dx) {
+                    int qx = m0[0] + dx - sx;
+                    if (wx == n2x) { qx %= n2x; if (qx < 0) qx += n2x; }
+                    if (qx < 0 || qx >= wx) continue;
+                    const T kx = ker[wv][dx];
+                    const cplx<T> gv = grid[((int64_t)qx * wy + qy) * wz + qz];
+                    sr += gv.x * kx;
+                    si += gv.y * kx;
                 }
-                ar += sr * kxy;
-                ai += si * kxy;
+                ar += sr * kyz;
+                ai += si * kyz;
             }
         }
         for (int off = 32; off > 0; off >>= 1) {
@@ -497,20 +542,50 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
 //   s_k.x_n = s_k.x_S + s_T.(x_n - x_S) + (s_k - s_T).(x_n - x_S):
 // the first two terms are evaluated once per (target, tile) and
 // (source, tile); only the small third term is evaluated per (target,
-// source) pair.  Phases are float64 (full rate on CDNA); the float32 plan
-// evaluates the reduced phase with the hardware sine / cosine, whose
-// argument is in revolutions.
+// source) pair.  The sign iota is folded into the staged values
+// (c exp(-i t) = conj(conj(c) exp(+i t))), so the inner loop always
+// accumulates c exp(+2 pi i t).  Phases are float64 (full rate on CDNA).
 // ---------------------------------------------------------------------------
+
+// exp(2 pi i t) for the float32 plan: fractional part in float64, then the
+// hardware sine / cosine, whose argument is in revolutions.
 __device__ __forceinline__ void cis_rev(double t, float &c, float &s)
 {
-    const float r = static_cast<float>(t - rint(t));
+    const float r = static_cast<float>(__builtin_amdgcn_fract(t));
     s = __builtin_amdgcn_sinf(r);
     c = __builtin_amdgcn_cosf(r);
 }
+
+// exp(2 pi i t) for the float64 plan: reduce t to the nearest quarter turn,
+// t = q/4 + f with |f| <= 1/8, evaluate sin and cos of theta = 2 pi f by their
+// Maclaurin series through theta^13 / theta^14 (truncation below 3e-14 on
+// |theta| <= pi/4), then rotate by q quarter turns.
 __device__ __forceinline__ void cis_rev(double t, double &c, double &s)
 {
-    const double r = t - rint(t);
-    sincospi(2.0 * r, &s, &c);
+    const double q = rint(4.0 * t);
+    const double f = fma(q, -0.25, t);
+    const double th = 6.283185307179586476925287 * f;
+    const double z = th * th;
+    double ps = 1.0 / 6227020800.0;                 // 1/13!
+    ps = fma(ps, -z, 1.0 / 39916800.0);             // 1/11!
+    ps = fma(ps, -z, 1.0 / 362880.0);               // 1/9!
+    ps = fma(ps, -z, 1.0 / 5040.0);                 // 1/7!
+    ps = fma(ps, -z, 1.0 / 120.0);                  // 1/5!
+    ps = fma(ps, -z, 1.0 / 6.0);                    // 1/3!
+    const double sn = fma(-ps * z, th, th);
+    double pc = 1.0 / 87178291200.0;                // 1/14!
+    pc = fma(pc, -z, 1.0 / 479001600.0);            // 1/12!
+    pc = fma(pc, -z, 1.0 / 3628800.0);              // 1/10!
+    pc = fma(pc, -z, 1.0 / 40320.0);                // 1/8!
+    pc = fma(pc, -z, 1.0 / 720.0);                  // 1/6!
+    pc = fma(pc, -z, 1.0 / 24.0);                   // 1/4!
+    pc = fma(pc, -z, 0.5);                          // 1/2!
+    const double cs = fma(-pc, z, 1.0);
+    const int k = static_cast<int>(q) & 3;
+    const double s1 = (k & 1) ? cs : sn;
+    const double c1 = (k & 1) ? sn : cs;
+    s = (k & 2) ? -s1 : s1;
+    c = (k == 1 || k == 2) ? -c1 : c1;
 }
 
 template <typename T>
@@ -531,9 +606,8 @@ __global__ __launch_bounds__(kDirectTile) void k_direct(const DirectItem *__rest
     for (int d = 0; d < 3; ++d) {
         sT[d] = txyz[d * ntgt + it.tgt_off];
         sk[d] = txyz[d * ntgt + k];
-        sp[d] = sk[d] - sT[d];
+        sp[d] = iota * (sk[d] - sT[d]);          // the sign enters through the phase
     }
-    const T sg = T(iota);
     double accr = 0.0, acci = 0.0;
     for (int s0 = 0; s0 < it.src_cnt; s0 += kDirectTile) {
         const int64_t nS = it.src_off + s0;
@@ -559,13 +633,12 @@ __global__ __launch_bounds__(kDirectTile) void k_direct(const DirectItem *__rest
         __syncthreads();
         T ar = T(0), ai = T(0);
         for (int j = 0; j < cnt; ++j) {
-            const double t = sp[0] * lx[j] + sp[1] * ly[j] + sp[2] * lz[j];
+            const double t = fma(sp[0], lx[j], fma(sp[1], ly[j], sp[2] * lz[j]));
             T cs, sn;
             cis_rev(t, cs, sn);
-            sn *= sg;
             const cplx<T> c = lc[j];
-            ar += c.x * cs - c.y * sn;
-            ai += c.x * sn + c.y * cs;
+            ar = fma(c.x, cs, fma(-c.y, sn, ar));
+            ai = fma(c.x, sn, fma(c.y, cs, ai));
         }
         double ph = 0.0;
         for (int d = 0; d < 3; ++d) ph += sk[d] * xS[d];
@@ -654,6 +727,16 @@ hipError_t launch_fft(const PairDev *pairs, const int64_t *prefix, int npairs, i
 }
 
 template <typename T>
+hipError_t launch_transpose(const PairDev *pairs, const int64_t *prefix, int npairs, int64_t tiles, void *ws,
+                            hipStream_t st)
+{
+    if (tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_transpose<T>, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, st, pairs, prefix, npairs,
+                       static_cast<cplx<T> *>(ws));
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_interp(const PairDev *pairs, const int64_t *prefix, int npairs, int64_t total, const double *xyz,
                          int64_t ntgt, const double *deconv, const void *ws, double *acc, int w, double beta,
                          double iota, hipStream_t st)
@@ -696,6 +779,8 @@ template hipError_t launch_fft<float>(const PairDev *, const int64_t *, int, int
                                       const double *, int, double, hipStream_t);
 template hipError_t launch_fft<double>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,
                                        const double *, int, double, hipStream_t);
+template hipError_t launch_transpose<float>(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
+template hipError_t launch_transpose<double>(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
 template hipError_t launch_interp<float>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
                                          const double *, const void *, double *, int, double, double, hipStream_t);
 template hipError_t launch_interp<double>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,

@@ -440,8 +440,8 @@ PairGeom pair_geometry(const double X[3], const double S[3], const Params &p)
     g.bx = wx * n1y * n1z;
     g.cy = wx * wy * n1z;
     g.dz = wx * wy * wz;
-    g.bufA = std::max(g.g1, g.cy);
-    g.bufB = std::max(g.bx, g.dz);
+    g.bufA = std::max(g.g1, std::max(g.bx, g.dz));
+    g.bufB = std::max(g.bx, g.cy);
     return g;
 }
 
@@ -467,7 +467,8 @@ double pair_nufft_seconds(const PairGeom &g, int64_t ns, int64_t nt, const Param
 {
     const Rates r = rates_for(p.dtype);
     const double delta = p.dtype == HVOX_F64 ? 16.0 : 8.0;
-    double b = delta * (static_cast<double>(g.g1) + g.g1 + 2.0 * g.bx + 2.0 * g.cy + g.dz);
+    // spread writes grid 1; x pass G1 -> Bx; transpose 2 Bx; y pass Bx -> Cy; z pass Cy -> Dz
+    double b = delta * (2.0 * g.g1 + 4.0 * g.bx + 2.0 * g.cy + g.dz);
     if (bytes) *bytes = b;
     const double w3 = static_cast<double>(p.w) * p.w * p.w, w23 = static_cast<double>(p.w2) * p.w2 * p.w2;
     return b / r.hbm_bytes_per_s + (ns * w3 + nt * w23) / r.cells_per_s + r.pair_overhead_s;
@@ -534,6 +535,7 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
     dp->pre_pts.clear();
     dp->pre_tgts.clear();
     dp->pre_stiles.clear();
+    dp->pre_ttiles.clear();
     dp->tiles_total = 0;
     for (int q = 0; q < 3; ++q) dp->pre_tiles[q].clear();
     const int64_t cap = static_cast<int64_t>(hp.ws_elems);
@@ -555,6 +557,8 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
         b.pre_tgts = static_cast<int64_t>(dp->pre_tgts.size());
         b.pre_stiles = static_cast<int64_t>(dp->pre_stiles.size());
         dp->pre_stiles.push_back(0);
+        b.pre_ttiles = static_cast<int64_t>(dp->pre_ttiles.size());
+        dp->pre_ttiles.push_back(0);
         for (int q = 0; q < 3; ++q) b.pre_tiles[q] = static_cast<int64_t>(dp->pre_tiles[q].size());
         dp->pre_pts.push_back(0);
         dp->pre_tgts.push_back(0);
@@ -603,8 +607,12 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
             offA += g.bufA;
             offB += g.bufB;
             int64_t lines[3] = {static_cast<int64_t>(g.n1[2]) * g.n1[1],
-                                static_cast<int64_t>(g.wcount[0]) * g.n1[2],
-                                static_cast<int64_t>(g.wcount[1]) * g.wcount[0]};
+                                static_cast<int64_t>(g.n1[2]) * g.wcount[0],
+                                static_cast<int64_t>(g.wcount[0]) * g.wcount[1]};
+            const int64_t ntt = static_cast<int64_t>(g.n1[2]) * ((g.n1[1] + kTransposeTile - 1) / kTransposeTile) *
+                                ((g.wcount[0] + kTransposeTile - 1) / kTransposeTile);
+            b.ttiles += ntt;
+            dp->pre_ttiles.push_back(dp->pre_ttiles.back() + ntt);
             for (int q = 0; q < 3; ++q) {
                 int64_t L = pd.lines_per_tile[q];
                 int64_t tiles = (lines[q] + L - 1) / L;
@@ -623,6 +631,7 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
             // (coordinates, permutation, value, tile record) per tile it touches
             dp->alg_bytes[HVOX_K_SPREAD] += pd.src_cnt * (24.0 + 4.0 + 4.0 + delta) + delta * static_cast<double>(g.g1);
             dp->alg_bytes[HVOX_K_FFT_X] += delta * (static_cast<double>(g.g1) + g.bx);
+            dp->alg_bytes[HVOX_K_TRANSPOSE] += delta * 2.0 * static_cast<double>(g.bx);
             dp->alg_bytes[HVOX_K_FFT_Y] += delta * (static_cast<double>(g.bx) + g.cy);
             dp->alg_bytes[HVOX_K_FFT_Z] += delta * (static_cast<double>(g.cy) + g.dz);
             dp->alg_bytes[HVOX_K_INTERP] += pd.tgt_cnt * (24.0 + 8.0 + 16.0) +

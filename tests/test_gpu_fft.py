@@ -19,7 +19,7 @@ def fft_pass(x, n, wstart, wcount, sign, dtype):
     cd = torch.complex128 if dtype == "f64" else torch.complex64
     nlines, nin = x.shape
     xin = torch.as_tensor(x).to(device="cuda", dtype=cd).contiguous()
-    out = torch.zeros((wcount, nlines), dtype=cd, device="cuda")
+    out = torch.zeros((nlines, wcount), dtype=cd, device="cuda")
     st = torch.cuda.current_stream().cuda_stream
     rc = f(1 if dtype == "f64" else 0, n, nin, nlines, wstart, wcount, sign,
            ctypes.c_void_p(xin.data_ptr()), ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st))
@@ -32,7 +32,7 @@ def reference(x, n, wstart, wcount, sign):
     l = np.arange(nin) - nin // 2
     m = (wstart + np.arange(wcount)) % n
     E = np.exp(sign * 2j * np.pi * np.outer(l, m) / n)
-    return (x @ E).T
+    return x @ E
 
 
 @pytest.fixture(scope="module", autouse=True)
