@@ -148,6 +148,24 @@ def cpu_baseline(wl, target_s=12.0):
     return info, (rv, Vs), (rp, Is)
 
 
+def serving_run():
+    """64 Poisson-arriving requests (mean gap 10 ms), each a synthesis or an
+    analysis with log-uniform 1e4..1e6 visibilities and pixels on subsampled
+    SKA-like / LOFAR-like baselines, float32 at eps = 1e-4, through the
+    continuous-batching server; latency from arrival to observed completion."""
+    from paper_2306_06007_amd import serve
+    from paper_2306_06007_amd import workloads as W
+    reqs = W.serving_requests(seed=4)
+    log(f"serving: {len(reqs)} requests generated")
+    ex = serve.GpuExecutor(eps=1e-4, dtype="f32", slots=4, planners=8, workspace_bytes=1 << 30)
+    srv = serve.Server(ex, hbm_budget_bytes=64e9)
+    res = srv.run(reqs, keep_outputs=False)
+    ex.close()
+    s = serve.summarize(res)
+    s["max_in_flight"] = max(n for _, _, n, _ in srv.log)
+    return s
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +173,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--f64-steps", type=int, default=0, help="timed float64 steps (default: max(1, steps // 5))")
+    ap.add_argument("--direct-threshold", type=float, default=-1.0,
+                    help="per-sub-problem NUFFT/direct choice: <0 automatic (default), 0 forced NUFFT, inf all direct")
+    ap.add_argument("--serving", action="store_true", help="also run the 64-request serving workload (p50/p99)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build runs the whole transform on a single MI355X "
@@ -177,7 +198,7 @@ def main():
     for dtype, eps in (("f32", 1e-4), ("f64", 1e-9)):
         cd = torch.complex64 if dtype == "f32" else torch.complex128
         t0 = time.perf_counter()
-        plan = hv.Plan(wl.uvw, wl.xyz, eps, dtype)
+        plan = hv.Plan(wl.uvw, wl.xyz, eps, dtype, direct_threshold=args.direct_threshold)
         plan_s = time.perf_counter() - t0
         bufs = (torch.as_tensor(wl.sky).to("cuda", cd), torch.as_tensor(wl.vis).to("cuda", cd),
                 torch.empty((1, wl.n_vis), dtype=cd, device="cuda"),
@@ -222,10 +243,14 @@ def main():
         "plan": {d: {k: results[d]["info"][k] for k in ("n_vis_chunks", "n_sky_chunks", "n_pairs_nufft",
                                                           "n_pairs_direct", "w", "w2", "sigma", "sigma2",
                                                           "grid_cells", "direct_terms")} for d in results},
-        "kernels_ms": {d: {k: round(v["ms"], 3) for k, v in results[d]["stats"].items() if v["launches"]}
-                       for d in results},
+        "kernels": {d: {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
+                            "GB_s": round(v["alg_bytes"] / (v["ms"] * 1e6), 1) if v["ms"] > 0 and v["alg_bytes"] else None}
+                        for k, v in results[d]["stats"].items() if v["launches"]} for d in results},
+        "mode": {"direct_threshold": args.direct_threshold},
         "source_hash": kernel_source_hash(),
     }
+    if args.serving:
+        out["serving"] = serving_run()
     if not args.no_cpu_baseline:
         import oracle
         log("cpu baseline (oracle on sampled rows)...")

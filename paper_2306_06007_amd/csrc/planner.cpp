@@ -24,8 +24,11 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// Cost-model rates (seconds per unit) used to choose NUFFT or direct
-// summation for each sub-problem; calibrated against MI355X kernel timings.
+// Cost-model rates used to choose NUFFT or direct summation for each
+// sub-problem, calibrated against MI355X kernel timings of the 995k x 1M
+// SKA-like workload: the NUFFT kernels (spread, FFT passes, transpose,
+// interpolation) together sustained ~1.5e12 algorithmic bytes/s; the direct
+// kernel 2.7e12 (float32) and 8e11 (float64) terms/s.
 struct Rates {
     double hbm_bytes_per_s;     // effective streaming rate of the grid passes
     double cells_per_s;         // spread/interp kernel-cell updates
@@ -35,8 +38,8 @@ struct Rates {
 
 Rates rates_for(int dtype)
 {
-    if (dtype == HVOX_F64) return {3.0e12, 6.0e10, 1.2e11, 4e-6};
-    return {3.0e12, 1.2e11, 1.5e12, 4e-6};
+    if (dtype == HVOX_F64) return {1.5e12, 1.0e11, 8.0e11, 4e-6};
+    return {1.5e12, 2.0e11, 2.7e12, 4e-6};
 }
 
 }  // namespace
