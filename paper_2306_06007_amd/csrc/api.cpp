@@ -23,9 +23,9 @@ hipError_t launch_bin(const PairDev *pairs, const int64_t *prefix, int npairs, i
                       int64_t nsrc, int w, int32_t *counts, unsigned long long *cursor, int32_t *records,
                       hipStream_t st);
 template <typename T>
-hipError_t launch_spread(const PairDev *, const int64_t *, int, int64_t, const int64_t *, const int32_t *,
-                         const double *, int64_t, const int32_t *, const void *, void *, int, double, double,
-                         hipStream_t);
+hipError_t launch_spread(const PairDev *, const int64_t *, int, int64_t, const int64_t *, const int64_t *,
+                         const int32_t *, const double *, int64_t, const int32_t *, const void *, void *, int, double,
+                         double, hipStream_t);
 template <typename T>
 hipError_t launch_fft(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *, const double *, int,
                       double, hipStream_t);
@@ -59,6 +59,7 @@ struct DevDir {
     int64_t *pre_ttiles = nullptr;   // per batch: transpose-tile prefix over its pairs
     int64_t *tile_off = nullptr;     // [tiles_total + 1] record offsets of every grid-1 tile
     int32_t *records = nullptr;      // source indices listed per tile (plan-resident binning)
+    int64_t *tile_list = nullptr;    // non-empty tiles of sparse batches (batch-local indices)
 };
 
 struct TimedLaunch {
@@ -221,10 +222,23 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
         for (const Batch &b : dp.batches) {
             const PairDev *pairs = dd.pairs + b.pair0;
             const int np = static_cast<int>(b.npairs);
-            HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
-                return launch_spread<T>(pairs, dd.pre_stiles + b.pre_stiles, np, b.stiles, dd.tile_off, dd.records,
-                                        sxyz, n_src, sperm, in_t, pl->ws, p.w, p.beta, iota, st);
-            }));
+            if (b.sparse) {
+                // mostly empty grid 1: clear the batch's grid-1 region, then spread the listed tiles
+                HVOX_TRY(timed(pl, HVOX_K_ZERO, st, [&] {
+                    return launch_zero(static_cast<double *>(pl->ws),
+                                       b.g_cnt * static_cast<int64_t>(sizeof(C) / sizeof(double)), st);
+                }));
+                HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
+                    return launch_spread<T>(pairs, dd.pre_stiles + b.pre_stiles, np, b.list_cnt,
+                                            dd.tile_list + b.list_off, dd.tile_off, dd.records, sxyz, n_src, sperm,
+                                            in_t, pl->ws, p.w, p.beta, iota, st);
+                }));
+            } else {
+                HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
+                    return launch_spread<T>(pairs, dd.pre_stiles + b.pre_stiles, np, b.stiles, nullptr, dd.tile_off,
+                                            dd.records, sxyz, n_src, sperm, in_t, pl->ws, p.w, p.beta, iota, st);
+                }));
+            }
             for (int pass = 0; pass < 3; ++pass) {
                 HVOX_TRY(timed(pl, HVOX_K_FFT_X + pass, st, [&] {
                     return launch_fft<T>(pairs, dd.pre_tiles[pass] + b.pre_tiles[pass], np, b.tiles[pass], pass,
@@ -291,7 +305,7 @@ int upload_dir(hvox_plan_s *pl, const DirPlan &dp, DevDir *dd, hipStream_t st)
 // Plan-time binning of every NUFFT sub-problem's sources to the grid-1 tiles
 // their footprints touch (count, host prefix sum, scatter); the per-tile
 // lists stay resident and drive the tiled spreading kernel.
-int bin_direction(hvox_plan_s *pl, const DirPlan &dp, DevDir *dd, const double *sxyz, int64_t n_src, hipStream_t st,
+int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, int64_t n_src, hipStream_t st,
                   std::string *err)
 {
     if (dp.tiles_total == 0) return HVOX_OK;
@@ -321,6 +335,24 @@ int bin_direction(hvox_plan_s *pl, const DirPlan &dp, DevDir *dd, const double *
     if (e != hipSuccess) return bad(e, "binning count pass");
     std::vector<int64_t> off(nt + 1, 0);
     for (int64_t i = 0; i < nt; ++i) off[i + 1] = off[i] + counts[i];
+    // batches whose grid 1 is mostly empty: clear it with one fill, spread only the non-empty tiles
+    dp.tile_list.clear();
+    for (Batch &b : dp.batches) {
+        const int64_t t0 = dp.pairs[b.pair0].tile0;
+        int64_t nonempty = 0;
+        for (int64_t t = 0; t < b.stiles; ++t) nonempty += counts[t0 + t] > 0;
+        b.sparse = 2 * nonempty < b.stiles;
+        b.list_off = static_cast<int64_t>(dp.tile_list.size());
+        b.list_cnt = 0;
+        if (!b.sparse) continue;
+        for (int64_t t = 0; t < b.stiles; ++t)
+            if (counts[t0 + t] > 0) dp.tile_list.push_back(t);
+        b.list_cnt = static_cast<int64_t>(dp.tile_list.size()) - b.list_off;
+    }
+    if (!dp.tile_list.empty()) {
+        hipError_t el = upload(pl, dp.tile_list, &dd->tile_list, st);
+        if (el != hipSuccess) return bad(el, "tile list");
+    }
     e = upload(pl, off, &dd->tile_off, st);
     if (e != hipSuccess) return bad(e, "tile offsets");
     void *rec = nullptr;
@@ -711,7 +743,8 @@ extern "C" int hvox_test_fft(int32_t dtype, int32_t n, int32_t nin, int32_t nlin
     const int64_t lines = nlines;
     const int64_t tiles = (lines + pd.lines_per_tile[0] - 1) / pd.lines_per_tile[0];
     const int64_t gin = static_cast<int64_t>(nin) * nlines, gout = static_cast<int64_t>(wcount) * nlines;
-    pd.bufA = 0;
+    pd.bufG = 0;
+    pd.bufA = gin;
     pd.bufB = gin;
     pd.precor[0] = 0; pd.precor[1] = nin; pd.precor[2] = nin + nlines;
     pd.tw[0] = 0;

@@ -17,9 +17,12 @@ constexpr int kTransposeTile = 32;   // square tile of the transpose kernel
 constexpr int kFftElems = 4096;      // complex elements (lines x length) held in LDS by one workgroup
 constexpr int kFftMaxLen = 4096;     // longest 1D FFT (one line must fit a workgroup)
 constexpr int kFftMaxLines = 64;     // lines per FFT workgroup
-constexpr int kDirectTile = 256;     // targets per direct-sum workgroup (one per thread)
+constexpr int kDirectThreads = 256;  // threads of a direct-sum workgroup
+constexpr int kDirectTile = 512;     // targets per direct-sum workgroup (two per thread)
+constexpr int kDirectSrcTile = 256;  // sources staged in LDS at a time
 constexpr int kDirectSeg = 2048;     // sources per direct-sum work item
-constexpr int kWavesPerBlock = 4;    // interp: one wavefront per target
+constexpr int kInterpLanes = 16;     // interp: lanes per target
+constexpr int kInterpTargets = 256 / kInterpLanes;   // interp: targets per 256-thread workgroup
 constexpr int kMaxStages = 16;       // radix stages per FFT length
 // spreading gathers by grid-1 tile: one 256-thread workgroup per tile of
 // kTileX x kTileY x kTileZ cells, each thread owning one x-y column of kTileZ
@@ -52,9 +55,10 @@ struct PairDev {
     int32_t wcount[3];           // kept FFT outputs per dimension
     int32_t nrad[3];             // radix stages per dimension
     int32_t lines_per_tile[3];   // FFT lines per workgroup, per pass
-    int64_t bufA, bufB;          // complex-element offsets of the two grid buffers in the workspace:
-                                 //   A: grid 1 [n1z][n1y][n1x] -> x-pass output transposed [n1z][wx][n1y]
-                                 //      -> z-pass output [wx][wy][wz] (read by the interpolation)
+    int64_t bufG, bufA, bufB;    // complex-element offsets of the grid buffers in the workspace:
+                                 //   G: grid 1 [n1z][n1y][n1x] (spread output, x-pass input)
+                                 //   A: x-pass output transposed [n1z][wx][n1y] -> z-pass output
+                                 //      [wx][wy][wz] (read by the interpolation)
                                  //   B: x-pass output [n1z][n1y][wx] -> y-pass output [n1z][wx][wy]
     int64_t tile0;               // index of the pair's first grid-1 tile among the direction's tiles
     int32_t ntile[3];            // grid-1 tiles per dimension
@@ -90,6 +94,9 @@ struct Batch {
     int64_t stiles = 0;                  // spreading tiles (workgroups)
     int64_t pre_stiles = 0;              // offset of the batch's tile prefix array
     int64_t ttiles = 0;                  // transpose tiles (workgroups)
+    int64_t g_cnt = 0;                   // complex elements of the batch's grid-1 region (starts at 0)
+    bool sparse = false;                 // spread only the non-empty tiles after clearing the grid-1 region
+    int64_t list_off = 0, list_cnt = 0;  // the batch's non-empty tiles in the direction's tile list
     int64_t pre_ttiles = 0;              // offset of the batch's transpose-tile prefix array
     int64_t ws_end = 0;                  // end of the batch's workspace use (complex elements)
     int64_t pre_pts = 0, pre_tgts = 0;   // offsets into the prefix arrays
@@ -105,6 +112,7 @@ struct DirPlan {                         // one direction (synthesis or analysis
     std::vector<int64_t> pre_stiles;     // per batch: npairs+1 prefix sums of spreading tiles
     std::vector<int64_t> pre_ttiles;     // per batch: npairs+1 prefix sums of transpose tiles
     int64_t tiles_total = 0;             // spreading tiles over all batches
+    std::vector<int64_t> tile_list;      // batch-local indices of non-empty tiles of sparse batches
     std::vector<DirectItem> direct;
     double grid_cells = 0.0, direct_terms = 0.0;
     double est_seconds = 0.0;

@@ -166,7 +166,8 @@ __global__ void k_bin_points(const PairDev *__restrict__ pairs, const int64_t *_
 // pass, no atomics, and for a given plan the result is deterministic).
 template <typename T>
 __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pairs, const int64_t *__restrict__ tprefix,
-                                                int npairs, const int64_t *__restrict__ toff,
+                                                int npairs, const int64_t *__restrict__ tile_list,
+                                                const int64_t *__restrict__ toff,
                                                 const int32_t *__restrict__ records, const double *__restrict__ xyz,
                                                 int64_t nsrc, const int32_t *__restrict__ perm,
                                                 const cplx<T> *__restrict__ in, cplx<T> *__restrict__ ws, int w, T beta,
@@ -177,9 +178,10 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
     __shared__ cplx<T> val[kSpreadBatch];
     __shared__ int org[kSpreadBatch][3];
     const int tid = threadIdx.x;
-    const int p = (int)find_segment(tprefix, npairs, blockIdx.x);
+    const int64_t bt = tile_list ? tile_list[blockIdx.x] : (int64_t)blockIdx.x;   // batch-local tile
+    const int p = (int)find_segment(tprefix, npairs, bt);
     const PairDev &P = pairs[p];
-    const int64_t lt = (int64_t)blockIdx.x - tprefix[p];
+    const int64_t lt = bt - tprefix[p];
     const int tx = (int)(lt % P.ntile[0]);
     const int ty = (int)((lt / P.ntile[0]) % P.ntile[1]);
     const int tz = (int)(lt / ((int64_t)P.ntile[0] * P.ntile[1]));
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
     }
     const int gx = ox + x, gy = oy + y;
     if (gx < P.n1[0] && gy < P.n1[1]) {
-        cplx<T> *grid = ws + P.bufA;
+        cplx<T> *grid = ws + P.bufG;
 #pragma unroll
         for (int z = 0; z < kTileZ; ++z) {
             const int gz = oz + z;
@@ -362,7 +364,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restr
     int64_t lines;
     const cplx<T> *src;
     cplx<T> *dst;
-    if (pass == 0) { lines = (int64_t)P.n1[2] * P.n1[1]; src = ws + P.bufA; dst = ws + P.bufB; }
+    if (pass == 0) { lines = (int64_t)P.n1[2] * P.n1[1]; src = ws + P.bufG; dst = ws + P.bufB; }
     else if (pass == 1) { lines = (int64_t)P.n1[2] * P.wcount[0]; src = ws + P.bufA; dst = ws + P.bufB; }
     else { lines = (int64_t)P.wcount[0] * P.wcount[1]; src = ws + P.bufB; dst = ws + P.bufA; }
     const int L = P.lines_per_tile[pass];
@@ -451,8 +453,9 @@ __global__ __launch_bounds__(256) void k_transpose(const PairDev *__restrict__ p
 // ---------------------------------------------------------------------------
 // interpolation + deconvolution + post-phase (type-3 steps 3-4):
 //   f_k += exp(2 pi i iota s_k.x_c) / prod Psi_hat(.) * sum_m G_m prod_d ES((m_d - tau_kd) 2/w)
-// One wavefront per target; lanes cover the (y, z) pairs of its w^3 window
-// (z fastest, as the grid), loop over x, and reduce across the wavefront.  Accumulation is float64
+// A group of kInterpLanes lanes per target (four targets per wavefront);
+// the lanes cover the (y, z) pairs of its w^3 window (z fastest, as the
+// grid), loop over x, and reduce across the group.  Accumulation is float64
 // (cross-sub-problem sums stay in double precision).
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -461,12 +464,12 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
                                                 const double *__restrict__ deconv, const cplx<T> *__restrict__ ws,
                                                 double *__restrict__ acc, int w, T beta, double iota)
 {
-    __shared__ T ker[kWavesPerBlock][3 * kWMax];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ T ker[kInterpTargets][3 * kWMax];
+    const int sub = threadIdx.x & (kInterpLanes - 1), slot = threadIdx.x / kInterpLanes;
     const T two_over_w = T(2) / T(w);
-    for (int64_t base = (int64_t)blockIdx.x * kWavesPerBlock; base < total;
-         base += (int64_t)gridDim.x * kWavesPerBlock) {
-        const int64_t g = base + wv;
+    for (int64_t base = (int64_t)blockIdx.x * kInterpTargets; base < total;
+         base += (int64_t)gridDim.x * kInterpTargets) {
+        const int64_t g = base + slot;
         const bool active = g < total;
         int p = 0;
         int64_t k = 0;
@@ -480,10 +483,10 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
                 tau[d] = (xyz[d * ntgt + k] - P.sc[d]) * P.tscale[d];
                 m0[d] = (int)ceil(tau[d] - 0.5 * w);
             }
-            if (lane < 3 * w) {
-                int d = lane / w, q = lane - d * w;
-                T off = T((double)(m0[d] + q) - tau[d]);
-                ker[wv][lane] = es_kernel(off * two_over_w, beta);
+            for (int q = sub; q < 3 * w; q += kInterpLanes) {
+                const int d = q / w, r = q - d * w;
+                const T off = T((double)(m0[d] + r) - tau[d]);
+                ker[slot][q] = es_kernel(off * two_over_w, beta);
             }
         }
         __syncthreads();
@@ -494,20 +497,22 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
             const int n2x = P.n2[0], n2y = P.n2[1], n2z = P.n2[2];
             const int sx = P.wstart[0], sy = P.wstart[1], sz = P.wstart[2];
             const cplx<T> *grid = ws + P.bufA;          // [wx][wy][wz], z fastest
-            for (int e = lane; e < w * w; e += 64) {
+            for (int e = sub; e < w * w; e += kInterpLanes) {
                 const int dy = e / w, dz = e - dy * w;
                 int qy = m0[1] + dy - sy, qz = m0[2] + dz - sz;
                 if (wy == n2y) { qy %= n2y; if (qy < 0) qy += n2y; }
                 if (wz == n2z) { qz %= n2z; if (qz < 0) qz += n2z; }
                 if (qy < 0 || qy >= wy || qz < 0 || qz >= wz) continue;
-                const T kyz = ker[wv][w + dy] * ker[wv][2 * w + dz];
+                const T kyz = ker[slot][w + dy] * ker[slot][2 * w + dz];
+                const cplx<T> *col = grid + (int64_t)qy * wz + qz;
+                const int64_t xstride = (int64_t)wy * wz;
                 T sr = T(0), si = T(0);
                 for (int dx = 0; dx < w; ++dx) {
                     int qx = m0[0] + dx - sx;
                     if (wx == n2x) { qx %= n2x; if (qx < 0) qx += n2x; }
                     if (qx < 0 || qx >= wx) continue;
-                    const T kx = ker[wv][dx];
-                    const cplx<T> gv = grid[((int64_t)qx * wy + qy) * wz + qz];
+                    const T kx = ker[slot][dx];
+                    const cplx<T> gv = col[qx * xstride];
                     sr += gv.x * kx;
                     si += gv.y * kx;
                 }
@@ -515,11 +520,12 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
                 ai += si * kyz;
             }
         }
-        for (int off = 32; off > 0; off >>= 1) {
+        // reduce over the target's lane group (xor offsets below the group size stay inside it)
+        for (int off = kInterpLanes / 2; off > 0; off >>= 1) {
             ar += __shfl_xor(ar, off, 64);
             ai += __shfl_xor(ai, off, 64);
         }
-        if (active && lane == 0) {
+        if (active && sub == 0) {
             const PairDev &P = pairs[p];
             double ph = 0.0;
             for (int d = 0; d < 3; ++d) ph += xyz[d * ntgt + k] * P.xc[d];
@@ -536,8 +542,8 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
 // ---------------------------------------------------------------------------
 // direct evaluation of a sub-problem block (Sect. 3.1, last bullet; the
 // eps = 0 mode of Sect. 4):  f_k += sum_n c_n exp(2 pi i iota s_k.x_n).
-// A workgroup owns <= 256 targets (one per thread) and <= kDirectSeg
-// sources, staged 256 at a time in LDS.  Per source tile with reference
+// A workgroup of 256 threads owns <= 512 targets (two per thread) and
+// <= kDirectSeg sources, staged 256 at a time in LDS.  Per source tile with reference
 // point x_S and target-tile reference s_T,
 //   s_k.x_n = s_k.x_S + s_T.(x_n - x_S) + (s_k - s_T).(x_n - x_S):
 // the first two terms are evaluated once per (target, tile) and
@@ -589,31 +595,36 @@ __device__ __forceinline__ void cis_rev(double t, double &c, double &s)
 }
 
 template <typename T>
-__global__ __launch_bounds__(kDirectTile) void k_direct(const DirectItem *__restrict__ items,
-                                                        const double *__restrict__ sxyz, int64_t nsrc,
-                                                        const double *__restrict__ txyz, int64_t ntgt,
-                                                        const int32_t *__restrict__ perm,
-                                                        const cplx<T> *__restrict__ in, double *__restrict__ acc,
-                                                        double iota)
+__global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__restrict__ items,
+                                                           const double *__restrict__ sxyz, int64_t nsrc,
+                                                           const double *__restrict__ txyz, int64_t ntgt,
+                                                           const int32_t *__restrict__ perm,
+                                                           const cplx<T> *__restrict__ in, double *__restrict__ acc,
+                                                           double iota)
 {
-    __shared__ double lx[kDirectTile], ly[kDirectTile], lz[kDirectTile];
-    __shared__ cplx<T> lc[kDirectTile];
+    static_assert(kDirectSrcTile == kDirectThreads && kDirectTile == 2 * kDirectThreads, "direct tiling");
+    __shared__ double lx[kDirectSrcTile], ly[kDirectSrcTile], lz[kDirectSrcTile];
+    __shared__ cplx<T> lc[kDirectSrcTile];
     const DirectItem it = items[blockIdx.x];
     const int tid = threadIdx.x;
-    const bool has_t = tid < it.tgt_cnt;
-    const int64_t k = it.tgt_off + (has_t ? tid : 0);
-    double sT[3], sk[3], sp[3];
+    // two targets per thread: each staged source is read from LDS once for both
+    const bool has0 = tid < it.tgt_cnt, has1 = tid + kDirectThreads < it.tgt_cnt;
+    const int64_t k0 = it.tgt_off + (has0 ? tid : 0);
+    const int64_t k1 = it.tgt_off + (has1 ? tid + kDirectThreads : 0);
+    double sT[3], sk0[3], sk1[3], sp0[3], sp1[3];
     for (int d = 0; d < 3; ++d) {
         sT[d] = txyz[d * ntgt + it.tgt_off];
-        sk[d] = txyz[d * ntgt + k];
-        sp[d] = iota * (sk[d] - sT[d]);          // the sign enters through the phase
+        sk0[d] = txyz[d * ntgt + k0];
+        sk1[d] = txyz[d * ntgt + k1];
+        sp0[d] = iota * (sk0[d] - sT[d]);        // the sign enters through the phase
+        sp1[d] = iota * (sk1[d] - sT[d]);
     }
-    double accr = 0.0, acci = 0.0;
-    for (int s0 = 0; s0 < it.src_cnt; s0 += kDirectTile) {
+    double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
+    for (int s0 = 0; s0 < it.src_cnt; s0 += kDirectSrcTile) {
         const int64_t nS = it.src_off + s0;
         double xS[3];
         for (int d = 0; d < 3; ++d) xS[d] = sxyz[d * nsrc + nS];
-        const int cnt = min(kDirectTile, it.src_cnt - s0);
+        const int cnt = min(kDirectSrcTile, it.src_cnt - s0);
         __syncthreads();
         if (tid < cnt) {
             const int64_t n = nS + tid;
@@ -631,24 +642,38 @@ __global__ __launch_bounds__(kDirectTile) void k_direct(const DirectItem *__rest
             lc[tid] = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
         }
         __syncthreads();
-        T ar = T(0), ai = T(0);
+        T b0r = T(0), b0i = T(0), b1r = T(0), b1i = T(0);
         for (int j = 0; j < cnt; ++j) {
-            const double t = fma(sp[0], lx[j], fma(sp[1], ly[j], sp[2] * lz[j]));
-            T cs, sn;
-            cis_rev(t, cs, sn);
+            const double xj = lx[j], yj = ly[j], zj = lz[j];
             const cplx<T> c = lc[j];
-            ar = fma(c.x, cs, fma(-c.y, sn, ar));
-            ai = fma(c.x, sn, fma(c.y, cs, ai));
+            const double t0 = fma(sp0[0], xj, fma(sp0[1], yj, sp0[2] * zj));
+            const double t1 = fma(sp1[0], xj, fma(sp1[1], yj, sp1[2] * zj));
+            T c0, s0v, c1, s1v;
+            cis_rev(t0, c0, s0v);
+            cis_rev(t1, c1, s1v);
+            b0r = fma(c.x, c0, fma(-c.y, s0v, b0r));
+            b0i = fma(c.x, s0v, fma(c.y, c0, b0i));
+            b1r = fma(c.x, c1, fma(-c.y, s1v, b1r));
+            b1i = fma(c.x, s1v, fma(c.y, c1, b1i));
         }
-        double ph = 0.0;
-        for (int d = 0; d < 3; ++d) ph += sk[d] * xS[d];
-        const double2 e = cis_cycles(ph, iota);
-        accr += (double)ar * e.x - (double)ai * e.y;
-        acci += (double)ar * e.y + (double)ai * e.x;
+        double ph0 = 0.0, ph1 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            ph0 += sk0[d] * xS[d];
+            ph1 += sk1[d] * xS[d];
+        }
+        const double2 e0 = cis_cycles(ph0, iota), e1 = cis_cycles(ph1, iota);
+        a0r += (double)b0r * e0.x - (double)b0i * e0.y;
+        a0i += (double)b0r * e0.y + (double)b0i * e0.x;
+        a1r += (double)b1r * e1.x - (double)b1i * e1.y;
+        a1i += (double)b1r * e1.y + (double)b1i * e1.x;
     }
-    if (has_t) {
-        atomicAdd(acc + 2 * k, accr);
-        atomicAdd(acc + 2 * k + 1, acci);
+    if (has0) {
+        atomicAdd(acc + 2 * k0, a0r);
+        atomicAdd(acc + 2 * k0 + 1, a0i);
+    }
+    if (has1) {
+        atomicAdd(acc + 2 * k1, a1r);
+        atomicAdd(acc + 2 * k1 + 1, a1i);
     }
 }
 
@@ -704,14 +729,15 @@ hipError_t launch_bin(const PairDev *pairs, const int64_t *prefix, int npairs, i
 }
 
 template <typename T>
-hipError_t launch_spread(const PairDev *pairs, const int64_t *tprefix, int npairs, int64_t tiles, const int64_t *toff,
-                         const int32_t *records, const double *xyz, int64_t nsrc, const int32_t *perm, const void *in,
-                         void *ws, int w, double beta, double iota, hipStream_t st)
+hipError_t launch_spread(const PairDev *pairs, const int64_t *tprefix, int npairs, int64_t tiles,
+                         const int64_t *tile_list, const int64_t *toff, const int32_t *records, const double *xyz,
+                         int64_t nsrc, const int32_t *perm, const void *in, void *ws, int w, double beta, double iota,
+                         hipStream_t st)
 {
     if (tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_spread<T>, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, st, pairs, tprefix, npairs,
-                       toff, records, xyz, nsrc, perm, static_cast<const cplx<T> *>(in), static_cast<cplx<T> *>(ws), w,
-                       T(beta), iota);
+                       tile_list, toff, records, xyz, nsrc, perm, static_cast<const cplx<T> *>(in),
+                       static_cast<cplx<T> *>(ws), w, T(beta), iota);
     return hipGetLastError();
 }
 
@@ -742,7 +768,7 @@ hipError_t launch_interp(const PairDev *pairs, const int64_t *prefix, int npairs
                          double iota, hipStream_t st)
 {
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_interp<T>, dim3(blocks_for(total, kWavesPerBlock, 1 << 16)), dim3(256), 0, st, pairs,
+    hipLaunchKernelGGL(k_interp<T>, dim3(blocks_for(total, kInterpTargets, 1 << 16)), dim3(256), 0, st, pairs,
                        prefix, npairs, total, xyz, ntgt, deconv, static_cast<const cplx<T> *>(ws), acc, w, T(beta),
                        iota);
     return hipGetLastError();
@@ -754,7 +780,7 @@ hipError_t launch_direct(const DirectItem *items, int64_t nitems, const double *
                          double iota, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_direct<T>, dim3(static_cast<unsigned>(nitems)), dim3(kDirectTile), 0, st, items, sxyz,
+    hipLaunchKernelGGL(k_direct<T>, dim3(static_cast<unsigned>(nitems)), dim3(kDirectThreads), 0, st, items, sxyz,
                        nsrc, txyz, ntgt, perm, static_cast<const cplx<T> *>(in), acc, iota);
     return hipGetLastError();
 }
@@ -770,11 +796,11 @@ hipError_t launch_finalize(const double *acc, int64_t n, const int32_t *perm, vo
 }
 
 template hipError_t launch_spread<float>(const PairDev *, const int64_t *, int, int64_t, const int64_t *,
-                                         const int32_t *, const double *, int64_t, const int32_t *, const void *,
-                                         void *, int, double, double, hipStream_t);
+                                         const int64_t *, const int32_t *, const double *, int64_t, const int32_t *,
+                                         const void *, void *, int, double, double, hipStream_t);
 template hipError_t launch_spread<double>(const PairDev *, const int64_t *, int, int64_t, const int64_t *,
-                                          const int32_t *, const double *, int64_t, const int32_t *, const void *,
-                                          void *, int, double, double, hipStream_t);
+                                          const int64_t *, const int32_t *, const double *, int64_t,
+                                          const int32_t *, const void *, void *, int, double, double, hipStream_t);
 template hipError_t launch_fft<float>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,
                                       const double *, int, double, hipStream_t);
 template hipError_t launch_fft<double>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,

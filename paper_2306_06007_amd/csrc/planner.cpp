@@ -407,7 +407,7 @@ int build_chunkset(const double *x, int64_t n, const int32_t *labels, ChunkSet *
 struct PairGeom {
     int32_t n1[3], n2[3], wstart[3], wcount[3];
     double kscale[3], tscale[3];
-    int64_t g1, bx, cy, dz, bufA, bufB;
+    int64_t g1, bx, cy, dz, bufA, bufB;   // bufA, bufB exclude grid 1 (its own region)
     bool fits;
 };
 
@@ -443,7 +443,7 @@ PairGeom pair_geometry(const double X[3], const double S[3], const Params &p)
     g.bx = wx * n1y * n1z;
     g.cy = wx * wy * n1z;
     g.dz = wx * wy * wz;
-    g.bufA = std::max(g.g1, std::max(g.bx, g.dz));
+    g.bufA = std::max(g.bx, g.dz);
     g.bufB = std::max(g.bx, g.cy);
     return g;
 }
@@ -459,7 +459,7 @@ void floor_widths(double B[3], double P[3], double sigma)
     }
 }
 
-int64_t ws_of(const PairGeom &g) { return g.bufA + g.bufB; }
+int64_t ws_of(const PairGeom &g) { return g.g1 + g.bufA + g.bufB; }
 
 struct DirInputs {
     const ChunkSet *src, *tgt;
@@ -539,6 +539,7 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
     dp->pre_tgts.clear();
     dp->pre_stiles.clear();
     dp->pre_ttiles.clear();
+    dp->tile_list.clear();
     dp->tiles_total = 0;
     for (int q = 0; q < 3; ++q) dp->pre_tiles[q].clear();
     const int64_t cap = static_cast<int64_t>(hp.ws_elems);
@@ -546,15 +547,17 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
     while (k < nufft.size()) {
         Batch b;
         b.pair0 = static_cast<int64_t>(dp->pairs.size());
-        int64_t sumA = 0, sumB = 0;
+        int64_t sumG = 0, sumA = 0, sumB = 0;
         size_t k1 = k;
         while (k1 < nufft.size()) {
-            int64_t a = nufft[k1].g.bufA, bb = nufft[k1].g.bufB;
-            if (k1 > k && sumA + sumB + a + bb > cap) break;
+            const int64_t gg = nufft[k1].g.g1, a = nufft[k1].g.bufA, bb = nufft[k1].g.bufB;
+            if (k1 > k && sumG + sumA + sumB + gg + a + bb > cap) break;
+            sumG += gg;
             sumA += a;
             sumB += bb;
             ++k1;
         }
+        b.g_cnt = sumG;
         b.npairs = static_cast<int64_t>(k1 - k);
         b.pre_pts = static_cast<int64_t>(dp->pre_pts.size());
         b.pre_tgts = static_cast<int64_t>(dp->pre_tgts.size());
@@ -566,7 +569,7 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
         dp->pre_pts.push_back(0);
         dp->pre_tgts.push_back(0);
         for (int q = 0; q < 3; ++q) dp->pre_tiles[q].push_back(0);
-        int64_t offA = 0, offB = sumA;   // all grid-1 (A) buffers first, then the B buffers
+        int64_t offG = 0, offA = sumG, offB = sumG + sumA;   // grid-1 region, then the A and B buffers
         for (size_t m = k; m < k1; ++m) {
             const Cand &c = nufft[m];
             const PairGeom &g = c.g;
@@ -597,6 +600,7 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
                 pd.precor[d] = it->second;
                 if (tw_map->find(g.n2[d]) == tw_map->end()) tw_map->emplace(g.n2[d], 0);
             }
+            pd.bufG = offG;
             pd.bufA = offA;
             pd.bufB = offB;
             pd.ntile[0] = (g.n1[0] + kTileX - 1) / kTileX;
@@ -607,6 +611,7 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
             dp->tiles_total += nst;
             b.stiles += nst;
             dp->pre_stiles.push_back(dp->pre_stiles.back() + nst);
+            offG += g.g1;
             offA += g.bufA;
             offB += g.bufB;
             int64_t lines[3] = {static_cast<int64_t>(g.n1[2]) * g.n1[1],
