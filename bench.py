@@ -93,7 +93,7 @@ def kernel_table(plan, bufs):
 
 
 def roofline_entry(st, dtype):
-    hbm_kernels = ("zero", "spread", "fft_x", "fft_y", "fft_z", "interp", "finalize")
+    hbm_kernels = ("zero", "spread", "fft_x", "fft_y", "fft_z", "interp", "finalize", "transpose", "prephase")
     name = max(st, key=lambda k: st[k]["ms"])
     v = st[name]
     n = max(1, v["launches"])

@@ -130,7 +130,8 @@ typedef struct {
 #define HVOX_K_DIRECT   6
 #define HVOX_K_FINAL    7
 #define HVOX_K_TRANSPOSE 8
-#define HVOX_K_COUNT    9
+#define HVOX_K_PREPHASE 9   /* gather + pre-phase of the sources of a batch of sub-problems */
+#define HVOX_K_COUNT    10
 typedef struct {
     int64_t launches[HVOX_K_COUNT];
     double  ms[HVOX_K_COUNT];           /* summed HIP-event durations */

@@ -3,6 +3,7 @@
 // per-kernel HIP-event statistics.  No exception crosses the ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -23,9 +24,12 @@ hipError_t launch_bin(const PairDev *pairs, const int64_t *prefix, int npairs, i
                       int64_t nsrc, int w, int32_t *counts, unsigned long long *cursor, int32_t *records,
                       hipStream_t st);
 template <typename T>
-hipError_t launch_spread(const PairDev *, const int64_t *, int, int64_t, const int64_t *, const int64_t *,
-                         const int32_t *, const double *, int64_t, const int32_t *, const void *, void *, int, double,
-                         double, hipStream_t);
+hipError_t launch_prephase(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t, const int32_t *,
+                           const void *, void *, double, hipStream_t);
+template <typename T>
+hipError_t launch_spread(const PairDev *, const int32_t *, int64_t, const int64_t *, int64_t, const int64_t *,
+                         const int64_t *, const int32_t *, const double *, int64_t, const void *, void *, int, double,
+                         hipStream_t);
 template <typename T>
 hipError_t launch_fft(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *, const double *, int,
                       double, hipStream_t);
@@ -60,6 +64,7 @@ struct DevDir {
     int64_t *tile_off = nullptr;     // [tiles_total + 1] record offsets of every grid-1 tile
     int32_t *records = nullptr;      // source indices listed per tile (plan-resident binning)
     int64_t *tile_list = nullptr;    // non-empty tiles of sparse batches (batch-local indices)
+    int32_t *tile_pair = nullptr;    // [tiles_total] sub-problem of every grid-1 tile (index within its batch)
 };
 
 struct TimedLaunch {
@@ -82,6 +87,7 @@ struct hvox_plan_s {
     void *tw = nullptr;
     hvox::DevDir syn, ana;
     void *ws = nullptr;
+    void *stage = nullptr;                              // pre-phased source values of one batch
     double *acc = nullptr;
     hipStream_t last_stream = nullptr;
     double plan_seconds = 0.0;
@@ -222,6 +228,11 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
         for (const Batch &b : dp.batches) {
             const PairDev *pairs = dd.pairs + b.pair0;
             const int np = static_cast<int>(b.npairs);
+            const int64_t *pprefix = dd.pre_pts + b.pre_pts;
+            const int64_t tile_base = dp.pairs[b.pair0].tile0;
+            HVOX_TRY(timed(pl, HVOX_K_PREPHASE, st, [&] {
+                return launch_prephase<T>(pairs, pprefix, np, b.pts, sxyz, n_src, sperm, in_t, pl->stage, iota, st);
+            }));
             if (b.sparse) {
                 // mostly empty grid 1: clear the batch's grid-1 region, then spread the listed tiles
                 HVOX_TRY(timed(pl, HVOX_K_ZERO, st, [&] {
@@ -229,14 +240,14 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
                                        b.g_cnt * static_cast<int64_t>(sizeof(C) / sizeof(double)), st);
                 }));
                 HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
-                    return launch_spread<T>(pairs, dd.pre_stiles + b.pre_stiles, np, b.list_cnt,
-                                            dd.tile_list + b.list_off, dd.tile_off, dd.records, sxyz, n_src, sperm,
-                                            in_t, pl->ws, p.w, p.beta, iota, st);
+                    return launch_spread<T>(pairs, dd.tile_pair, tile_base, pprefix, b.list_cnt,
+                                            dd.tile_list + b.list_off, dd.tile_off, dd.records, sxyz, n_src,
+                                            pl->stage, pl->ws, p.w, p.beta, st);
                 }));
             } else {
                 HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
-                    return launch_spread<T>(pairs, dd.pre_stiles + b.pre_stiles, np, b.stiles, nullptr, dd.tile_off,
-                                            dd.records, sxyz, n_src, sperm, in_t, pl->ws, p.w, p.beta, iota, st);
+                    return launch_spread<T>(pairs, dd.tile_pair, tile_base, pprefix, b.stiles, nullptr, dd.tile_off,
+                                            dd.records, sxyz, n_src, pl->stage, pl->ws, p.w, p.beta, st);
                 }));
             }
             for (int pass = 0; pass < 3; ++pass) {
@@ -250,7 +261,7 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
                     }));
             }
             HVOX_TRY(timed(pl, HVOX_K_INTERP, st, [&] {
-                return launch_interp<T>(pairs, dd.pre_tgts + b.pre_tgts, np, b.tgts, txyz, n_tgt, dd.deconv, pl->ws,
+                return launch_interp<T>(pairs, dd.pre_tgts + b.pre_tgts, np, b.iblocks, txyz, n_tgt, dd.deconv, pl->ws,
                                         pl->acc, p.w2, p.beta2, iota, st);
             }));
         }
@@ -352,6 +363,19 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
     if (!dp.tile_list.empty()) {
         hipError_t el = upload(pl, dp.tile_list, &dd->tile_list, st);
         if (el != hipSuccess) return bad(el, "tile list");
+    }
+    {
+        // sub-problem of every tile, as an index into its batch's pairs
+        std::vector<int32_t> tp(nt);
+        for (const Batch &b : dp.batches)
+            for (int64_t i = 0; i < b.npairs; ++i) {
+                const PairDev &pd = dp.pairs[b.pair0 + i];
+                const int64_t n_tiles = static_cast<int64_t>(pd.ntile[0]) * pd.ntile[1] * pd.ntile[2];
+                std::fill(tp.begin() + pd.tile0, tp.begin() + pd.tile0 + n_tiles, static_cast<int32_t>(i));
+            }
+        hipError_t el = upload(pl, tp, &dd->tile_pair, st);
+        if (el == hipSuccess) el = hipStreamSynchronize(st);   // tp is released on return
+        if (el != hipSuccess) return bad(el, "tile table");
     }
     e = upload(pl, off, &dd->tile_off, st);
     if (e != hipSuccess) return bad(e, "tile offsets");
@@ -474,6 +498,10 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
     chk(dev_alloc(pl, 16 * static_cast<size_t>(std::max(hp.n_vis, hp.n_pix)), &tmp, true), "accumulator");
     pl->acc = static_cast<double *>(tmp);
     chk(dev_alloc(pl, delta * static_cast<size_t>(hp.ws_elems), &pl->ws, false), "workspace");
+    int64_t max_pts = 0;
+    for (const DirPlan *dp : {&hp.syn, &hp.ana})
+        for (const Batch &b : dp->batches) max_pts = std::max(max_pts, b.pts);
+    if (max_pts > 0) chk(dev_alloc(pl, delta * static_cast<size_t>(max_pts), &pl->stage, true), "source staging");
     if (rc) return rc;
     chk(hipStreamSynchronize(st), "plan upload");
     return rc;

@@ -90,6 +90,7 @@ struct ChunkSet {
 struct Batch {
     int64_t pair0 = 0, npairs = 0;       // range in the direction's PairDev array
     int64_t pts = 0, tgts = 0;           // spread points, interp targets
+    int64_t iblocks = 0;                 // interp workgroups (kInterpTargets targets of one pair each)
     int64_t tiles[3] = {0, 0, 0};        // FFT workgroups per pass
     int64_t stiles = 0;                  // spreading tiles (workgroups)
     int64_t pre_stiles = 0;              // offset of the batch's tile prefix array
@@ -99,7 +100,7 @@ struct Batch {
     int64_t list_off = 0, list_cnt = 0;  // the batch's non-empty tiles in the direction's tile list
     int64_t pre_ttiles = 0;              // offset of the batch's transpose-tile prefix array
     int64_t ws_end = 0;                  // end of the batch's workspace use (complex elements)
-    int64_t pre_pts = 0, pre_tgts = 0;   // offsets into the prefix arrays
+    int64_t pre_pts = 0, pre_tgts = 0;   // offsets into the prefix arrays (pre_tgts: interp workgroups)
     int64_t pre_tiles[3] = {0, 0, 0};
     int32_t lds_elems[3] = {0, 0, 0};    // largest LDS need per pass (complex elements)
     int32_t max_pass_len[3] = {0, 0, 0};
@@ -108,7 +109,8 @@ struct Batch {
 struct DirPlan {                         // one direction (synthesis or analysis)
     std::vector<PairDev> pairs;          // NUFFT sub-problems, batch-contiguous
     std::vector<Batch> batches;
-    std::vector<int64_t> pre_pts, pre_tgts, pre_tiles[3];   // per batch: npairs+1 prefix sums
+    std::vector<int64_t> pre_pts, pre_tgts, pre_tiles[3];   // per batch: npairs+1 prefix sums (points,
+                                                            // interp workgroups, FFT workgroups)
     std::vector<int64_t> pre_stiles;     // per batch: npairs+1 prefix sums of spreading tiles
     std::vector<int64_t> pre_ttiles;     // per batch: npairs+1 prefix sums of transpose tiles
     int64_t tiles_total = 0;             // spreading tiles over all batches

@@ -6,12 +6,13 @@
 //  * coordinates: float64 structure-of-arrays [3][n] in chunk order;
 //  * user data:   complex (float2 / double2) in user order, gathered through
 //                 the chunk-order permutation (Sect. 4, chunk-order views);
-//  * grids:       per sub-problem two buffers in one workspace.  Grid 1 is
-//                 [n1z][n1y][n1x]; every FFT pass reads contiguous lines and
-//                 writes its kept outputs transposed, rotating the axes
-//                 (x-pass -> [wx][n1z][n1y], y-pass -> [wy][wx][n1z],
-//                 z-pass -> [wz][wy][wx]) so the next pass reads contiguous
-//                 lines again and the interpolation reads an x-fastest grid;
+//  * grids:       per batch of sub-problems one workspace with three regions:
+//                 G holds every pair's grid 1 as [n1z][n1y][n1x]; the x pass
+//                 writes its kept window line-major to B ([n1z][n1y][wx]), a
+//                 tiled transpose moves it to A ([n1z][wx][n1y]), the y pass
+//                 writes B ([n1z][wx][wy]), and the z pass reads its lines
+//                 strided and writes A as [wx][wy][wz] (z fastest), which the
+//                 interpolation reads;
 //  * accumulator: float64 complex per target (chunk order).
 #include <hip/hip_runtime.h>
 
@@ -68,6 +69,16 @@ __device__ __forceinline__ int64_t find_segment(const int64_t *__restrict__ pref
     }
     return lo;
 }
+
+// floor(a / d) for 0 <= a < 2^21, given rd = 1/d as a float.  (a + 1/2) / d
+// is at least 1/(2d) away from every integer while the float product is off
+// by at most (a + 1/2) / d * 2^-22 < 1/(2d), so truncation gives the exact
+// quotient: a few full-rate instructions instead of a 32-bit integer division.
+__device__ __forceinline__ int small_div(int a, float rd)
+{
+    return static_cast<int>((static_cast<float>(a) + 0.5f) * rd);
+}
+static_assert(kFftElems < (1 << 21), "FFT workgroup indices must stay below 2^21 for small_div");
 
 // ---------------------------------------------------------------------------
 // fills
@@ -158,38 +169,63 @@ __global__ void k_bin_points(const PairDev *__restrict__ pairs, const int64_t *_
             }
 }
 
+// Gather + pre-phase of a batch's sources (type-3 centring, the source side):
+// c'_n = c_perm(n) exp(2 pi i iota s_c.(x_n - x_c)) for every source of every
+// sub-problem of the batch, in the batch's order (sub-problem, then chunk
+// order).  The phase is float64.
+template <typename T>
+__global__ void k_prephase(const PairDev *__restrict__ pairs, const int64_t *__restrict__ pprefix, int npairs,
+                           int64_t total, const double *__restrict__ xyz, int64_t nsrc,
+                           const int32_t *__restrict__ perm, const cplx<T> *__restrict__ in,
+                           cplx<T> *__restrict__ stage, double iota)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int p = (int)find_segment(pprefix, npairs, g);
+    const PairDev &P = pairs[p];
+    const int64_t n = P.src_off + (g - pprefix[p]);
+    double ph = 0.0;
+    for (int d = 0; d < 3; ++d) ph += P.sc[d] * (xyz[d * nsrc + n] - P.xc[d]);
+    const double2 e = cis_cycles(ph, iota);
+    const cplx<T> c = in[perm[n]];
+    stage[g] = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
+}
+
 // One workgroup per grid-1 tile.  Thread (x, y) of the 32 x 8 face owns the
 // kTileZ cells of its column; the tile's sources are staged kSpreadBatch at a
 // time (their pre-phased values, footprint origin and 3w kernel values in
 // LDS), every thread adds the contributions that fall in its cells, and the
-// whole tile is written once (empty tiles write zeros: no separate clearing
-// pass, no atomics, and for a given plan the result is deterministic).
+// whole tile is written once (no atomics; for a given plan the result is
+// deterministic).  The tile's sub-problem comes from a plan-time table, its
+// source list from the plan-time binning, the values from the pre-phase pass.
 template <typename T>
-__global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pairs, const int64_t *__restrict__ tprefix,
-                                                int npairs, const int64_t *__restrict__ tile_list,
+__global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pairs, const int32_t *__restrict__ tile_pair,
+                                                int64_t tile_base, const int64_t *__restrict__ pprefix,
+                                                const int64_t *__restrict__ tile_list,
                                                 const int64_t *__restrict__ toff,
                                                 const int32_t *__restrict__ records, const double *__restrict__ xyz,
-                                                int64_t nsrc, const int32_t *__restrict__ perm,
-                                                const cplx<T> *__restrict__ in, cplx<T> *__restrict__ ws, int w, T beta,
-                                                double iota)
+                                                int64_t nsrc, const cplx<T> *__restrict__ stage,
+                                                cplx<T> *__restrict__ ws, int w, T beta)
 {
     __shared__ T ker[kSpreadBatch][3 * kWMax];
     __shared__ T frac[kSpreadBatch][3];
     __shared__ cplx<T> val[kSpreadBatch];
     __shared__ int org[kSpreadBatch][3];
     const int tid = threadIdx.x;
-    const int64_t bt = tile_list ? tile_list[blockIdx.x] : (int64_t)blockIdx.x;   // batch-local tile
-    const int p = (int)find_segment(tprefix, npairs, bt);
+    const int64_t gt = tile_base + (tile_list ? tile_list[blockIdx.x] : (int64_t)blockIdx.x);
+    const int p = tile_pair[gt];
+    const int64_t r0 = toff[gt], r1 = toff[gt + 1];
     const PairDev &P = pairs[p];
-    const int64_t lt = bt - tprefix[p];
+    const int64_t lt = gt - P.tile0;
     const int tx = (int)(lt % P.ntile[0]);
     const int ty = (int)((lt / P.ntile[0]) % P.ntile[1]);
     const int tz = (int)(lt / ((int64_t)P.ntile[0] * P.ntile[1]));
     const int ox = tx * kTileX, oy = ty * kTileY, oz = tz * kTileZ;
     const int x = tid % kTileX, y = tid / kTileX;
-    const int64_t gtile = P.tile0 + lt;
-    const int64_t r0 = toff[gtile], r1 = toff[gtile + 1];
     const T two_over_w = T(2) / T(w);
+    const int w3 = 3 * w;
+    const float rw = 1.0f / static_cast<float>(w), rw3 = 1.0f / static_cast<float>(w3);
+    const cplx<T> *sv = stage + pprefix[p] - P.src_off;   // staged value of source n: sv[n]
     T accr[kTileZ], acci[kTileZ];
 #pragma unroll
     for (int z = 0; z < kTileZ; ++z) accr[z] = acci[z] = T(0);
@@ -202,21 +238,16 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
             double xp[3], t[3];
             int c0[3];
             source_footprint(P, xyz, nsrc, n, w, xp, t, c0);
-            double ph = 0.0;
-            for (int d = 0; d < 3; ++d) {
-                ph += P.sc[d] * xp[d];
-                frac[tid][d] = T((double)(c0[d] - P.n1[d] / 2) - t[d]);
-            }
+            for (int d = 0; d < 3; ++d) frac[tid][d] = T((double)(c0[d] - P.n1[d] / 2) - t[d]);
             org[tid][0] = c0[0] - ox;
             org[tid][1] = c0[1] - oy;
             org[tid][2] = c0[2] - oz;
-            const double2 e = cis_cycles(ph, iota);
-            const cplx<T> c = in[perm[n]];
-            val[tid] = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
+            val[tid] = sv[n];
         }
         __syncthreads();
-        for (int i = tid; i < cnt * 3 * w; i += 256) {
-            const int j = i / (3 * w), r = i - j * 3 * w, d = r / w, q = r - d * w;
+        for (int i = tid; i < cnt * w3; i += 256) {
+            const int j = small_div(i, rw3), r = i - __mul24(j, w3);
+            const int d = small_div(r, rw), q = r - __mul24(d, w);
             ker[j][r] = es_kernel((frac[j][d] + T(q)) * two_over_w, beta);
         }
         __syncthreads();
@@ -303,19 +334,25 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int p, const cplx<T> *__r
     const int nbf = n / R;
     const int total = nl * nbf;
     const int twstep = n / (p * R);
+    const int pR = p * R;
+    const float rnbf = 1.0f / static_cast<float>(nbf), rp = 1.0f / static_cast<float>(p);
     cplx<T> v[MAXB][R];
+    int obase[MAXB];
 #pragma unroll
     for (int c = 0; c < MAXB; ++c) {
         const int b = threadIdx.x + c * kFftThreads;
+        obase[c] = -1;
         if (b < total) {
-            const int j = b / nbf, i = b - j * nbf;
-            const int k = i % p;
-            const cplx<T> *line = lds + j * n;
+            const int j = small_div(b, rnbf), i = b - __mul24(j, nbf);
+            const int g = small_div(i, rp), k = i - __mul24(g, p);
+            const int lb = __mul24(j, n);
+            obase[c] = lb + __mul24(g, pR) + k;
+            const int tk = __mul24(k, twstep);
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                cplx<T> u = line[i + q * nbf];
+                cplx<T> u = lds[lb + i + q * nbf];
                 if (q > 0) {
-                    cplx<T> t = tw[k * q * twstep];
+                    cplx<T> t = tw[q * tk];
                     t.y *= -s;   // table holds exp(-2 pi i j/n); sign s = -1 keeps it, +1 conjugates
                     u = cmul<T>(u, t);
                 }
@@ -327,14 +364,9 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int p, const cplx<T> *__r
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < MAXB; ++c) {
-        const int b = threadIdx.x + c * kFftThreads;
-        if (b < total) {
-            const int j = b / nbf, i = b - j * nbf;
-            const int k = i % p;
-            cplx<T> *line = lds + j * n;
-            const int o = (i - k) * R + k;
+        if (obase[c] >= 0) {
 #pragma unroll
-            for (int m = 0; m < R; ++m) line[o + m * p] = v[c][m];
+            for (int m = 0; m < R; ++m) lds[obase[c] + m * p] = v[c][m];
         }
     }
     __syncthreads();
@@ -346,8 +378,9 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int p, const cplx<T> *__r
 // read contiguous lines; the z pass reads its lines strided (line j of the
 // plane is element j of every z-slab, so consecutive lines sit in adjacent
 // lanes).  The x pass also applies the separable pre-correction
-// 1/Phi_hat(l/n2) of all three axes.  Output q of the kept window is FFT index
-// (wstart + q) mod n, written line-major: out[line][q].
+// 1/Phi_hat(l/n2) of all three axes (the (y, z) factor once per line).  Output
+// q of the kept window is FFT index (wstart + q) mod n, written line-major:
+// out[line][q].
 template <typename T>
 __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restrict__ pairs,
                                                           const int64_t *__restrict__ prefix, int npairs, int pass,
@@ -356,6 +389,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restr
 {
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *lds = reinterpret_cast<cplx<T> *>(smem_raw);
+    __shared__ T lfac[kFftMaxLines];
     const int p = (int)find_segment(prefix, npairs, blockIdx.x);
     const PairDev &P = pairs[p];
     const int64_t tile = (int64_t)blockIdx.x - prefix[p];
@@ -370,32 +404,39 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restr
     const int L = P.lines_per_tile[pass];
     const int64_t line0 = tile * L;
     const int nl = (int)min((int64_t)L, lines - line0);
-    const int half_in = nin / 2;
+    const int half_in = nin / 2, half_n = n / 2;
 
+    if (pass == 0) {
+        if ((int)threadIdx.x < nl) {
+            const int64_t li = line0 + threadIdx.x;
+            const int64_t lz = li / P.n1[1], ly = li - lz * P.n1[1];
+            lfac[threadIdx.x] = T(precor[P.precor[1] + ly] * precor[P.precor[2] + lz]);
+        }
+        __syncthreads();
+    }
     if (pass < 2) {
+        const cplx<T> *sb = src + line0 * nin;
+        const double *px = precor + P.precor[0] + half_in;
+        const float rn = 1.0f / static_cast<float>(n);
         for (int e = threadIdx.x; e < nl * n; e += kFftThreads) {
-            const int j = e / n, f = e - j * n;
-            const int l = f < n / 2 ? f : f - n;
+            const int j = small_div(e, rn), f = e - __mul24(j, n);
+            const int l = f < half_n ? f : f - n;
             cplx<T> v = mk<T>(T(0), T(0));
             if (l >= -half_in && l < half_in) {
-                const int64_t li = line0 + j;
-                v = src[li * nin + (l + half_in)];
-                if (pass == 0) {
-                    const int64_t lz = li / P.n1[1], ly = li - lz * P.n1[1];
-                    const double fac = precor[P.precor[0] + l + half_in] * precor[P.precor[1] + ly] *
-                                       precor[P.precor[2] + lz];
-                    v = cscale<T>(v, T(fac));
-                }
+                v = sb[__mul24(j, nin) + l + half_in];
+                if (pass == 0) v = cscale<T>(v, T(px[l]) * lfac[j]);
             }
-            lds[j * n + f] = v;
+            lds[e] = v;
         }
     } else {
+        const cplx<T> *sb = src + line0;
+        const float rl = 1.0f / static_cast<float>(nl);
         for (int e = threadIdx.x; e < nl * n; e += kFftThreads) {
-            const int f = e / nl, j = e - f * nl;
-            const int l = f < n / 2 ? f : f - n;
+            const int f = small_div(e, rl), j = e - __mul24(f, nl);
+            const int l = f < half_n ? f : f - n;
             cplx<T> v = mk<T>(T(0), T(0));
-            if (l >= -half_in && l < half_in) v = src[(int64_t)(l + half_in) * lines + line0 + j];
-            lds[j * n + f] = v;
+            if (l >= -half_in && l < half_in) v = sb[(int64_t)(l + half_in) * lines + j];
+            lds[__mul24(j, n) + f] = v;
         }
     }
     __syncthreads();
@@ -409,12 +450,14 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restr
         else fft_stage<T, 5>(lds, nl, n, pc, tw, s);
         pc *= R;
     }
+    // kept window: wstart is 0 (whole line) or -R with 2R < n, so wstart + q lies in (-n, n)
     cplx<T> *out = dst + line0 * wcnt;
+    const float rw = 1.0f / static_cast<float>(wcnt);
     for (int e = threadIdx.x; e < nl * wcnt; e += kFftThreads) {
-        const int j = e / wcnt, q = e - j * wcnt;
-        int m = (wst + q) % n;
+        const int j = small_div(e, rw), q = e - __mul24(j, wcnt);
+        int m = wst + q;
         if (m < 0) m += n;
-        out[e] = lds[j * n + m];
+        out[e] = lds[__mul24(j, n) + m];
     }
 }
 
@@ -451,108 +494,9 @@ __global__ __launch_bounds__(256) void k_transpose(const PairDev *__restrict__ p
 }
 
 // ---------------------------------------------------------------------------
-// interpolation + deconvolution + post-phase (type-3 steps 3-4):
-//   f_k += exp(2 pi i iota s_k.x_c) / prod Psi_hat(.) * sum_m G_m prod_d ES((m_d - tau_kd) 2/w)
-// A group of kInterpLanes lanes per target (four targets per wavefront);
-// the lanes cover the (y, z) pairs of its w^3 window (z fastest, as the
-// grid), loop over x, and reduce across the group.  Accumulation is float64
-// (cross-sub-problem sums stay in double precision).
+// exp(2 pi i t) with t in revolutions, t reduced in float64 (phases of the
+// interpolation epilogue and of the direct sum).
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pairs, const int64_t *__restrict__ prefix,
-                                                int npairs, int64_t total, const double *__restrict__ xyz, int64_t ntgt,
-                                                const double *__restrict__ deconv, const cplx<T> *__restrict__ ws,
-                                                double *__restrict__ acc, int w, T beta, double iota)
-{
-    __shared__ T ker[kInterpTargets][3 * kWMax];
-    const int sub = threadIdx.x & (kInterpLanes - 1), slot = threadIdx.x / kInterpLanes;
-    const T two_over_w = T(2) / T(w);
-    for (int64_t base = (int64_t)blockIdx.x * kInterpTargets; base < total;
-         base += (int64_t)gridDim.x * kInterpTargets) {
-        const int64_t g = base + slot;
-        const bool active = g < total;
-        int p = 0;
-        int64_t k = 0;
-        int m0[3] = {0, 0, 0};
-        if (active) {
-            p = (int)find_segment(prefix, npairs, g);
-            const PairDev &P = pairs[p];
-            k = P.tgt_off + (g - prefix[p]);
-            double tau[3];
-            for (int d = 0; d < 3; ++d) {
-                tau[d] = (xyz[d * ntgt + k] - P.sc[d]) * P.tscale[d];
-                m0[d] = (int)ceil(tau[d] - 0.5 * w);
-            }
-            for (int q = sub; q < 3 * w; q += kInterpLanes) {
-                const int d = q / w, r = q - d * w;
-                const T off = T((double)(m0[d] + r) - tau[d]);
-                ker[slot][q] = es_kernel(off * two_over_w, beta);
-            }
-        }
-        __syncthreads();
-        T ar = T(0), ai = T(0);
-        if (active) {
-            const PairDev &P = pairs[p];
-            const int wx = P.wcount[0], wy = P.wcount[1], wz = P.wcount[2];
-            const int n2x = P.n2[0], n2y = P.n2[1], n2z = P.n2[2];
-            const int sx = P.wstart[0], sy = P.wstart[1], sz = P.wstart[2];
-            const cplx<T> *grid = ws + P.bufA;          // [wx][wy][wz], z fastest
-            for (int e = sub; e < w * w; e += kInterpLanes) {
-                const int dy = e / w, dz = e - dy * w;
-                int qy = m0[1] + dy - sy, qz = m0[2] + dz - sz;
-                if (wy == n2y) { qy %= n2y; if (qy < 0) qy += n2y; }
-                if (wz == n2z) { qz %= n2z; if (qz < 0) qz += n2z; }
-                if (qy < 0 || qy >= wy || qz < 0 || qz >= wz) continue;
-                const T kyz = ker[slot][w + dy] * ker[slot][2 * w + dz];
-                const cplx<T> *col = grid + (int64_t)qy * wz + qz;
-                const int64_t xstride = (int64_t)wy * wz;
-                T sr = T(0), si = T(0);
-                for (int dx = 0; dx < w; ++dx) {
-                    int qx = m0[0] + dx - sx;
-                    if (wx == n2x) { qx %= n2x; if (qx < 0) qx += n2x; }
-                    if (qx < 0 || qx >= wx) continue;
-                    const T kx = ker[slot][dx];
-                    const cplx<T> gv = col[qx * xstride];
-                    sr += gv.x * kx;
-                    si += gv.y * kx;
-                }
-                ar += sr * kyz;
-                ai += si * kyz;
-            }
-        }
-        // reduce over the target's lane group (xor offsets below the group size stay inside it)
-        for (int off = kInterpLanes / 2; off > 0; off >>= 1) {
-            ar += __shfl_xor(ar, off, 64);
-            ai += __shfl_xor(ai, off, 64);
-        }
-        if (active && sub == 0) {
-            const PairDev &P = pairs[p];
-            double ph = 0.0;
-            for (int d = 0; d < 3; ++d) ph += xyz[d * ntgt + k] * P.xc[d];
-            const double2 e = cis_cycles(ph, iota);
-            const double dk = deconv[k];
-            const double vr = (double)ar * dk, vi = (double)ai * dk;
-            atomicAdd(acc + 2 * k, vr * e.x - vi * e.y);
-            atomicAdd(acc + 2 * k + 1, vr * e.y + vi * e.x);
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
-// direct evaluation of a sub-problem block (Sect. 3.1, last bullet; the
-// eps = 0 mode of Sect. 4):  f_k += sum_n c_n exp(2 pi i iota s_k.x_n).
-// A workgroup of 256 threads owns <= 512 targets (two per thread) and
-// <= kDirectSeg sources, staged 256 at a time in LDS.  Per source tile with reference
-// point x_S and target-tile reference s_T,
-//   s_k.x_n = s_k.x_S + s_T.(x_n - x_S) + (s_k - s_T).(x_n - x_S):
-// the first two terms are evaluated once per (target, tile) and
-// (source, tile); only the small third term is evaluated per (target,
-// source) pair.  The sign iota is folded into the staged values
-// (c exp(-i t) = conj(conj(c) exp(+i t))), so the inner loop always
-// accumulates c exp(+2 pi i t).  Phases are float64 (full rate on CDNA).
-// ---------------------------------------------------------------------------
-
 // exp(2 pi i t) for the float32 plan: fractional part in float64, then the
 // hardware sine / cosine, whose argument is in revolutions.
 __device__ __forceinline__ void cis_rev(double t, float &c, float &s)
@@ -593,6 +537,100 @@ __device__ __forceinline__ void cis_rev(double t, double &c, double &s)
     s = (k & 2) ? -s1 : s1;
     c = (k == 1 || k == 2) ? -c1 : c1;
 }
+
+// ---------------------------------------------------------------------------
+// interpolation + deconvolution + post-phase (type-3 steps 3-4):
+//   f_k += exp(2 pi i iota s_k.x_c) / prod Psi_hat(.) * sum_m G_m prod_d ES((m_d - tau_kd) 2/w)
+// A group of kInterpLanes lanes per target (four targets per wavefront,
+// kInterpTargets targets of one sub-problem per workgroup);
+// the lanes cover the (y, z) pairs of its w^3 window (z fastest, as the
+// grid), loop over x, and reduce across the group.  Accumulation is float64
+// (cross-sub-problem sums stay in double precision).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pairs, const int64_t *__restrict__ bprefix,
+                                                int npairs, const double *__restrict__ xyz, int64_t ntgt,
+                                                const double *__restrict__ deconv, const cplx<T> *__restrict__ ws,
+                                                double *__restrict__ acc, int w, T beta, double iota)
+{
+    __shared__ T ker[kInterpTargets][3 * kWMax];
+    const int sub = threadIdx.x & (kInterpLanes - 1), slot = threadIdx.x / kInterpLanes;
+    const T two_over_w = T(2) / T(w);
+    // every workgroup serves kInterpTargets consecutive targets of one sub-problem
+    const int p = (int)find_segment(bprefix, npairs, blockIdx.x);
+    const PairDev &P = pairs[p];
+    const int64_t local = ((int64_t)blockIdx.x - bprefix[p]) * kInterpTargets + slot;
+    const bool active = local < P.tgt_cnt;
+    const int64_t k = P.tgt_off + (active ? local : 0);
+    double s_k[3];
+    int m0[3];
+    for (int d = 0; d < 3; ++d) {
+        s_k[d] = xyz[d * ntgt + k];
+        const double tau = (s_k[d] - P.sc[d]) * P.tscale[d];
+        m0[d] = (int)ceil(tau - 0.5 * w);
+        for (int q = sub; q < w; q += kInterpLanes)
+            ker[slot][d * w + q] = es_kernel(T((double)(m0[d] + q) - tau) * two_over_w, beta);
+    }
+    __syncthreads();
+    T ar = T(0), ai = T(0);
+    if (active) {
+        const int wx = P.wcount[0], wy = P.wcount[1], wz = P.wcount[2];
+        const int n2x = P.n2[0], n2y = P.n2[1], n2z = P.n2[2];
+        const int sx = P.wstart[0], sy = P.wstart[1], sz = P.wstart[2];
+        const cplx<T> *grid = ws + P.bufA;          // [wx][wy][wz], z fastest
+        const int64_t xstride = (int64_t)wy * wz;
+        for (int e = sub; e < w * w; e += kInterpLanes) {
+            const int dy = e / w, dz = e - dy * w;
+            int qy = m0[1] + dy - sy, qz = m0[2] + dz - sz;
+            if (wy == n2y) { qy %= n2y; if (qy < 0) qy += n2y; }
+            if (wz == n2z) { qz %= n2z; if (qz < 0) qz += n2z; }
+            if (qy < 0 || qy >= wy || qz < 0 || qz >= wz) continue;
+            const T kyz = ker[slot][w + dy] * ker[slot][2 * w + dz];
+            const cplx<T> *col = grid + (int64_t)qy * wz + qz;
+            T sr = T(0), si = T(0);
+            for (int dx = 0; dx < w; ++dx) {
+                int qx = m0[0] + dx - sx;
+                if (wx == n2x) { qx %= n2x; if (qx < 0) qx += n2x; }
+                if (qx < 0 || qx >= wx) continue;
+                const T kx = ker[slot][dx];
+                const cplx<T> gv = col[qx * xstride];
+                sr += gv.x * kx;
+                si += gv.y * kx;
+            }
+            ar += sr * kyz;
+            ai += si * kyz;
+        }
+    }
+    // reduce over the target's lane group (xor offsets below the group size stay inside it)
+    for (int off = kInterpLanes / 2; off > 0; off >>= 1) {
+        ar += __shfl_xor(ar, off, 64);
+        ai += __shfl_xor(ai, off, 64);
+    }
+    if (active && sub == 0) {
+        double ph = 0.0;
+        for (int d = 0; d < 3; ++d) ph += s_k[d] * P.xc[d];
+        T er, ei;
+        cis_rev(iota * ph, er, ei);
+        const double dk = deconv[k];
+        const double vr = (double)ar * dk, vi = (double)ai * dk;
+        atomicAdd(acc + 2 * k, vr * (double)er - vi * (double)ei);
+        atomicAdd(acc + 2 * k + 1, vr * (double)ei + vi * (double)er);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// direct evaluation of a sub-problem block (Sect. 3.1, last bullet; the
+// eps = 0 mode of Sect. 4):  f_k += sum_n c_n exp(2 pi i iota s_k.x_n).
+// A workgroup of 256 threads owns <= 512 targets (two per thread) and
+// <= kDirectSeg sources, staged 256 at a time in LDS.  Per source tile with reference
+// point x_S and target-tile reference s_T,
+//   s_k.x_n = s_k.x_S + s_T.(x_n - x_S) + (s_k - s_T).(x_n - x_S):
+// the first two terms are evaluated once per (target, tile) and
+// (source, tile); only the small third term is evaluated per (target,
+// source) pair.  The sign iota is folded into the staged values
+// (c exp(-i t) = conj(conj(c) exp(+i t))), so the inner loop always
+// accumulates c exp(+2 pi i t).  Phases are float64 (full rate on CDNA).
+// ---------------------------------------------------------------------------
 
 template <typename T>
 __global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__restrict__ items,
@@ -729,15 +767,26 @@ hipError_t launch_bin(const PairDev *pairs, const int64_t *prefix, int npairs, i
 }
 
 template <typename T>
-hipError_t launch_spread(const PairDev *pairs, const int64_t *tprefix, int npairs, int64_t tiles,
-                         const int64_t *tile_list, const int64_t *toff, const int32_t *records, const double *xyz,
-                         int64_t nsrc, const int32_t *perm, const void *in, void *ws, int w, double beta, double iota,
+hipError_t launch_prephase(const PairDev *pairs, const int64_t *pprefix, int npairs, int64_t total, const double *xyz,
+                           int64_t nsrc, const int32_t *perm, const void *in, void *stage, double iota, hipStream_t st)
+{
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prephase<T>, dim3(blocks_for(total, 256, INT32_MAX)), dim3(256), 0, st, pairs, pprefix,
+                       npairs, total, xyz, nsrc, perm, static_cast<const cplx<T> *>(in), static_cast<cplx<T> *>(stage),
+                       iota);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spread(const PairDev *pairs, const int32_t *tile_pair, int64_t tile_base, const int64_t *pprefix,
+                         int64_t tiles, const int64_t *tile_list, const int64_t *toff, const int32_t *records,
+                         const double *xyz, int64_t nsrc, const void *stage, void *ws, int w, double beta,
                          hipStream_t st)
 {
     if (tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spread<T>, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, st, pairs, tprefix, npairs,
-                       tile_list, toff, records, xyz, nsrc, perm, static_cast<const cplx<T> *>(in),
-                       static_cast<cplx<T> *>(ws), w, T(beta), iota);
+    hipLaunchKernelGGL(k_spread<T>, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, st, pairs, tile_pair, tile_base,
+                       pprefix, tile_list, toff, records, xyz, nsrc, static_cast<const cplx<T> *>(stage),
+                       static_cast<cplx<T> *>(ws), w, T(beta));
     return hipGetLastError();
 }
 
@@ -763,14 +812,13 @@ hipError_t launch_transpose(const PairDev *pairs, const int64_t *prefix, int npa
 }
 
 template <typename T>
-hipError_t launch_interp(const PairDev *pairs, const int64_t *prefix, int npairs, int64_t total, const double *xyz,
+hipError_t launch_interp(const PairDev *pairs, const int64_t *bprefix, int npairs, int64_t blocks, const double *xyz,
                          int64_t ntgt, const double *deconv, const void *ws, double *acc, int w, double beta,
                          double iota, hipStream_t st)
 {
-    if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_interp<T>, dim3(blocks_for(total, kInterpTargets, 1 << 16)), dim3(256), 0, st, pairs,
-                       prefix, npairs, total, xyz, ntgt, deconv, static_cast<const cplx<T> *>(ws), acc, w, T(beta),
-                       iota);
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_interp<T>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, pairs, bprefix, npairs,
+                       xyz, ntgt, deconv, static_cast<const cplx<T> *>(ws), acc, w, T(beta), iota);
     return hipGetLastError();
 }
 
@@ -795,12 +843,16 @@ hipError_t launch_finalize(const double *acc, int64_t n, const int32_t *perm, vo
     return hipGetLastError();
 }
 
-template hipError_t launch_spread<float>(const PairDev *, const int64_t *, int, int64_t, const int64_t *,
-                                         const int64_t *, const int32_t *, const double *, int64_t, const int32_t *,
-                                         const void *, void *, int, double, double, hipStream_t);
-template hipError_t launch_spread<double>(const PairDev *, const int64_t *, int, int64_t, const int64_t *,
-                                          const int64_t *, const int32_t *, const double *, int64_t,
-                                          const int32_t *, const void *, void *, int, double, double, hipStream_t);
+template hipError_t launch_prephase<float>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
+                                           const int32_t *, const void *, void *, double, hipStream_t);
+template hipError_t launch_prephase<double>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
+                                            const int32_t *, const void *, void *, double, hipStream_t);
+template hipError_t launch_spread<float>(const PairDev *, const int32_t *, int64_t, const int64_t *, int64_t,
+                                         const int64_t *, const int64_t *, const int32_t *, const double *, int64_t,
+                                         const void *, void *, int, double, hipStream_t);
+template hipError_t launch_spread<double>(const PairDev *, const int32_t *, int64_t, const int64_t *, int64_t,
+                                          const int64_t *, const int64_t *, const int32_t *, const double *, int64_t,
+                                          const void *, void *, int, double, hipStream_t);
 template hipError_t launch_fft<float>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,
                                       const double *, int, double, hipStream_t);
 template hipError_t launch_fft<double>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,

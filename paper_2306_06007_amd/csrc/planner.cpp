@@ -631,13 +631,18 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
             }
             b.pts += pd.src_cnt;
             b.tgts += pd.tgt_cnt;
+            const int64_t iblk = (pd.tgt_cnt + kInterpTargets - 1) / kInterpTargets;
+            b.iblocks += iblk;
             dp->pre_pts.push_back(dp->pre_pts.back() + pd.src_cnt);
-            dp->pre_tgts.push_back(dp->pre_tgts.back() + pd.tgt_cnt);
+            dp->pre_tgts.push_back(dp->pre_tgts.back() + iblk);
             dp->grid_cells += static_cast<double>(g.g1);
             // algorithmic HBM bytes per kernel (see the kernel documentation)
             // spreading writes every grid-1 cell once and reads each source
             // (coordinates, permutation, value, tile record) per tile it touches
-            dp->alg_bytes[HVOX_K_SPREAD] += pd.src_cnt * (24.0 + 4.0 + 4.0 + delta) + delta * static_cast<double>(g.g1);
+            // gather + pre-phase: coordinates, permutation, input value, staged value per source
+            dp->alg_bytes[HVOX_K_PREPHASE] += pd.src_cnt * (24.0 + 4.0 + 2.0 * delta);
+            // spreading: tile record, coordinates and staged value per source, grid 1 written once
+            dp->alg_bytes[HVOX_K_SPREAD] += pd.src_cnt * (4.0 + 24.0 + delta) + delta * static_cast<double>(g.g1);
             dp->alg_bytes[HVOX_K_FFT_X] += delta * (static_cast<double>(g.g1) + g.bx);
             dp->alg_bytes[HVOX_K_TRANSPOSE] += delta * 2.0 * static_cast<double>(g.bx);
             dp->alg_bytes[HVOX_K_FFT_Y] += delta * (static_cast<double>(g.bx) + g.cy);

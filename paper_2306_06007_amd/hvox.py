@@ -22,7 +22,7 @@ HVOX_REAL_SKY = 0x1
 HVOX_PLAN_HOST_ONLY = 0x2
 HVOX_TIMING = 0x4
 
-KERNELS = ("zero", "spread", "fft_x", "fft_y", "fft_z", "interp", "direct", "finalize", "transpose")
+KERNELS = ("zero", "spread", "fft_x", "fft_y", "fft_z", "interp", "direct", "finalize", "transpose", "prephase")
 
 ERRORS = {0: "HVOX_OK", -1: "HVOX_ERR_ARG", -2: "HVOX_ERR_EPS", -3: "HVOX_ERR_OOM",
           -4: "HVOX_ERR_HIP", -5: "HVOX_ERR_STATE"}
@@ -65,8 +65,8 @@ class HvoxPlanInfo(ctypes.Structure):
 
 
 class HvoxStats(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 9), ("ms", ctypes.c_double * 9),
-                ("alg_bytes", ctypes.c_double * 9), ("alg_flops", ctypes.c_double * 9)]
+    _fields_ = [("launches", ctypes.c_int64 * len(KERNELS)), ("ms", ctypes.c_double * len(KERNELS)),
+                ("alg_bytes", ctypes.c_double * len(KERNELS)), ("alg_flops", ctypes.c_double * len(KERNELS))]
 
 
 EXPORTS = ("hvox_plan", "hvox_synthesis", "hvox_analysis", "hvox_free", "hvox_plan_info",
