@@ -575,27 +575,39 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
     T ar = T(0), ai = T(0);
     if (active) {
         const int wx = P.wcount[0], wy = P.wcount[1], wz = P.wcount[2];
+        const bool fx = wx == P.n2[0], fy = wy == P.n2[1], fz = wz == P.n2[2];   // whole (periodic) axis kept
         const int n2x = P.n2[0], n2y = P.n2[1], n2z = P.n2[2];
         const int sx = P.wstart[0], sy = P.wstart[1], sz = P.wstart[2];
         const cplx<T> *grid = ws + P.bufA;          // [wx][wy][wz], z fastest
-        const int64_t xstride = (int64_t)wy * wz;
+        const int xstride = wy * wz;
         for (int e = sub; e < w * w; e += kInterpLanes) {
             const int dy = e / w, dz = e - dy * w;
             int qy = m0[1] + dy - sy, qz = m0[2] + dz - sz;
-            if (wy == n2y) { qy %= n2y; if (qy < 0) qy += n2y; }
-            if (wz == n2z) { qz %= n2z; if (qz < 0) qz += n2z; }
-            if (qy < 0 || qy >= wy || qz < 0 || qz >= wz) continue;
-            const T kyz = ker[slot][w + dy] * ker[slot][2 * w + dz];
-            const cplx<T> *col = grid + (int64_t)qy * wz + qz;
+            if (fy) { qy %= n2y; if (qy < 0) qy += n2y; }
+            if (fz) { qz %= n2z; if (qz < 0) qz += n2z; }
+            const bool ok = qy >= 0 && qy < wy && qz >= 0 && qz < wz;
+            const T kyz = ok ? ker[slot][w + dy] * ker[slot][2 * w + dz] : T(0);
+            const cplx<T> *col = grid + (ok ? qy * wz + qz : 0);
             T sr = T(0), si = T(0);
-            for (int dx = 0; dx < w; ++dx) {
-                int qx = m0[0] + dx - sx;
-                if (wx == n2x) { qx %= n2x; if (qx < 0) qx += n2x; }
-                if (qx < 0 || qx >= wx) continue;
-                const T kx = ker[slot][dx];
-                const cplx<T> gv = col[qx * xstride];
-                sr += gv.x * kx;
-                si += gv.y * kx;
+            // eight x cells at a time: cells outside the kept window get weight
+            // 0 and a valid address, so the loads carry no branches and issue together
+            for (int dx0 = 0; dx0 < w; dx0 += 8) {
+                cplx<T> gv[8];
+                T kx[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int dx = dx0 + u;
+                    int qx = m0[0] + dx - sx;
+                    if (fx) { qx %= n2x; if (qx < 0) qx += n2x; }
+                    const bool okx = dx < w && qx >= 0 && qx < wx;
+                    kx[u] = okx ? ker[slot][dx] : T(0);
+                    gv[u] = col[okx ? qx * xstride : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    sr += gv[u].x * kx[u];
+                    si += gv[u].y * kx[u];
+                }
             }
             ar += sr * kyz;
             ai += si * kyz;
