@@ -92,9 +92,16 @@ def kernel_table(plan, bufs):
     return st
 
 
-def roofline_entry(st, dtype):
-    hbm_kernels = ("zero", "spread", "fft_x", "fft_y", "fft_z", "interp", "finalize", "transpose", "prephase")
-    name = max(st, key=lambda k: st[k]["ms"])
+HBM_KERNELS = ("zero", "spread", "fft_x", "fft_y", "fft_z", "interp", "finalize", "transpose", "prephase")
+
+
+def roofline_entry(st, dtype, name=None):
+    """Roofline of one kernel (default: the one taking the most time): its
+    algorithmic bytes (or VALU lane-operations) per launch over its average
+    launch duration, against the MI355X peak."""
+    hbm_kernels = HBM_KERNELS
+    if name is None:
+        name = max(st, key=lambda k: st[k]["ms"])
     v = st[name]
     n = max(1, v["launches"])
     avg_s = v["ms"] * 1e-3 / n
@@ -113,12 +120,12 @@ def roofline_entry(st, dtype):
 
 # VALU instructions issued per (target, source) term by the direct kernel's
 # inner loop, counted from its gfx950 assembly (LDS reads and scalar loop
-# control excluded): float32 plan 45 per 4-term unrolled iteration (float64
-# dot and fractional part, conversion, hardware sine and cosine, complex
-# multiply-accumulate); float64 plan 86 per 2-term iteration (float64 dot,
-# quarter-turn reduction, Maclaurin sine and cosine, rotation, complex
-# multiply-accumulate).  Each is one lane-operation per lane.
-VALU_OPS_PER_TERM = {"f32": 45.0 / 4.0, "f64": 86.0 / 2.0}
+# control excluded): float32 plan 89 per unrolled iteration of 4 sources x 2
+# targets (float64 dot and fractional part, conversion, hardware sine and
+# cosine, complex multiply-accumulate); float64 plan 86 per 2-term iteration
+# (float64 dot, quarter-turn reduction, Maclaurin sine and cosine, rotation,
+# complex multiply-accumulate).  Each is one lane-operation per lane.
+VALU_OPS_PER_TERM = {"f32": 89.0 / 8.0, "f64": 86.0 / 2.0}
 
 
 def cpu_baseline(wl, target_s=12.0):
@@ -176,6 +183,10 @@ def main():
     ap.add_argument("--direct-threshold", type=float, default=-1.0,
                     help="per-sub-problem NUFFT/direct choice: <0 automatic (default), 0 forced NUFFT, inf all direct")
     ap.add_argument("--serving", action="store_true", help="also run the 64-request serving workload (p50/p99)")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the forced-NUFFT and all-direct float32 runs reported beside the headline")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB mebibytes three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build runs the whole transform on a single MI355X "
@@ -191,29 +202,51 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        # a plain copy of known size: what FETCH_SIZE / WRITE_SIZE read for it
+        # calibrates the counters that measure the kernels' HBM traffic
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "copies": 3}), flush=True)
+        return
     wl = W.ska_like()
     log(f"workload {wl.name}")
 
-    results = {}
-    for dtype, eps in (("f32", 1e-4), ("f64", 1e-9)):
+    def run_mode(dtype, eps, direct_threshold, steps, warm):
         cd = torch.complex64 if dtype == "f32" else torch.complex128
         t0 = time.perf_counter()
-        plan = hv.Plan(wl.uvw, wl.xyz, eps, dtype, direct_threshold=args.direct_threshold)
+        plan = hv.Plan(wl.uvw, wl.xyz, eps, dtype, direct_threshold=direct_threshold)
         plan_s = time.perf_counter() - t0
         bufs = (torch.as_tensor(wl.sky).to("cuda", cd), torch.as_tensor(wl.vis).to("cuda", cd),
                 torch.empty((1, wl.n_vis), dtype=cd, device="cuda"),
                 torch.empty((1, wl.n_pix), dtype=cd, device="cuda"))
-        steps = args.steps if dtype == "f32" else (args.f64_steps or max(1, args.steps // 5))
-        warm = args.warmup if dtype == "f32" else min(1, args.warmup)
         sec = time_steps(plan, bufs, steps, warm)
-        log(f"{dtype}: {sec * 1e3:.1f} ms/step over {steps} steps (plan {plan_s:.1f}s)")
+        log(f"{dtype} eps={eps:g} direct_threshold={direct_threshold:g}: {sec * 1e3:.1f} ms/step over {steps} "
+            f"steps (plan {plan_s:.1f}s)")
         st = kernel_table(plan, bufs)
         info = plan.info()
-        results[dtype] = dict(sec=sec, steps=steps, warmup=warm, plan_s=plan_s, stats=st, info=info,
-                              V=bufs[2][0].cpu().numpy(), I=bufs[3][0].cpu().numpy())
+        r = dict(sec=sec, steps=steps, warmup=warm, plan_s=plan_s, stats=st, info=info,
+                 V=bufs[2][0].cpu().numpy(), I=bufs[3][0].cpu().numpy())
         plan.free()
         del bufs
         torch.cuda.empty_cache()
+        return r
+
+    results = {
+        "f32": run_mode("f32", 1e-4, args.direct_threshold, args.steps, args.warmup),
+        "f64": run_mode("f64", 1e-9, args.direct_threshold, args.f64_steps or max(1, args.steps // 5),
+                        min(1, args.warmup)),
+    }
+    modes = {}
+    if not args.no_modes:
+        # the two other execution modes of the float32 transform: every sub-problem as a
+        # NUFFT (the path the spread / FFT / interp rooflines describe), every one direct
+        modes["forced_nufft"] = run_mode("f32", 1e-4, 0.0, 1, 0)
+        modes["all_direct"] = run_mode("f32", 0.0, -1.0, 1, 0)
 
     r32, r64 = results["f32"], results["f64"]
     n_units = wl.n_vis + wl.n_pix
@@ -249,6 +282,21 @@ def main():
         "mode": {"direct_threshold": args.direct_threshold},
         "source_hash": kernel_source_hash(),
     }
+    if modes:
+        out["modes"] = {}
+        for m, r in modes.items():
+            ent = {"ms_per_step": r["sec"] * 1e3, "value": n_units / r["sec"],
+                   "n_pairs_nufft": r["info"]["n_pairs_nufft"], "n_pairs_direct": r["info"]["n_pairs_direct"],
+                   "kernels": {k: {"ms": round(v["ms"], 3), "launches": v["launches"]}
+                               for k, v in r["stats"].items() if v["launches"]}}
+            roofs = {}
+            for k, v in r["stats"].items():
+                if v["launches"] and v["ms"] > 0 and (v["alg_bytes"] or k == "direct"):
+                    _, rf = roofline_entry(r["stats"], "f32", k)
+                    roofs[k] = {"bound": rf["bound"], "achieved": round(rf["achieved"], 1), "unit": rf["unit"],
+                                "frac": round(rf["frac"], 4)}
+            ent["rooflines"] = roofs
+            out["modes"][m] = ent
     if args.serving:
         out["serving"] = serving_run()
     if not args.no_cpu_baseline:
@@ -260,6 +308,9 @@ def main():
             d: {"synthesis": oracle.rel_l2(results[d]["V"][rv], Vs[0]),
                 "analysis": oracle.rel_l2(results[d]["I"][rp], Is[0]),
                 "rows": int(len(rv))} for d in results}
+        for m, r in modes.items():
+            out["modes"][m]["rel_l2_vs_oracle"] = {"synthesis": oracle.rel_l2(r["V"][rv], Vs[0]),
+                                                   "analysis": oracle.rel_l2(r["I"][rp], Is[0])}
     print(json.dumps(out), flush=True)
 
 
