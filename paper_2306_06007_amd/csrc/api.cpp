@@ -32,7 +32,7 @@ hipError_t launch_spread(const PairDev *, const int32_t *, int64_t, const int64_
                          hipStream_t);
 template <typename T>
 hipError_t launch_fft(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *, const double *, int,
-                      double, hipStream_t);
+                      int, double, hipStream_t);
 template <typename T>
 hipError_t launch_transpose(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
 template <typename T>
@@ -253,7 +253,8 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
             for (int pass = 0; pass < 3; ++pass) {
                 HVOX_TRY(timed(pl, HVOX_K_FFT_X + pass, st, [&] {
                     return launch_fft<T>(pairs, dd.pre_tiles[pass] + b.pre_tiles[pass], np, b.tiles[pass], pass,
-                                         pl->ws, pl->tw, pl->precor, b.lds_elems[pass], iota, st);
+                                         pl->ws, pl->tw, pl->precor, b.lds_elems[pass], b.max_pass_len[pass], iota,
+                                         st);
                 }));
                 if (pass == 0)
                     HVOX_TRY(timed(pl, HVOX_K_TRANSPOSE, st, [&] {
@@ -806,9 +807,9 @@ extern "C" int hvox_test_fft(int32_t dtype, int32_t n, int32_t nin, int32_t nlin
     if (e == hipSuccess)
         e = dtype == HVOX_F64
                 ? launch_fft<double>(static_cast<PairDev *>(d_pd), static_cast<int64_t *>(d_pre), 1, tiles, 0, d_ws,
-                                     d_tw, static_cast<double *>(d_one), lds, sign, st)
+                                     d_tw, static_cast<double *>(d_one), lds, n, sign, st)
                 : launch_fft<float>(static_cast<PairDev *>(d_pd), static_cast<int64_t *>(d_pre), 1, tiles, 0, d_ws,
-                                    d_tw, static_cast<double *>(d_one), lds, sign, st);
+                                    d_tw, static_cast<double *>(d_one), lds, n, sign, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(out, static_cast<char *>(d_ws) + delta * gin, delta * gout, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);

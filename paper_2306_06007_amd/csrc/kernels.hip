@@ -328,7 +328,7 @@ __device__ __forceinline__ void dft_small(cplx<T> *u, T s)
 // Butterfly i of a line: k = i mod p, inputs x[i + q n/R] twiddled by
 // w^(k q n / (p R)), outputs at (i - k) R + k + m p.
 template <typename T, int R>
-__device__ void fft_stage(cplx<T> *lds, int nl, int n, int p, const cplx<T> *__restrict__ tw, T s)
+__device__ void fft_stage(cplx<T> *lds, int nl, int n, int p, const cplx<T> *tw, T s)
 {
     constexpr int MAXB = (kFftElems / R + kFftThreads - 1) / kFftThreads;
     const int nbf = n / R;
@@ -348,12 +348,16 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int p, const cplx<T> *__r
             const int lb = __mul24(j, n);
             obase[c] = lb + __mul24(g, pR) + k;
             const int tk = __mul24(k, twstep);
+            const int half = n >> 1;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 cplx<T> u = lds[lb + i + q * nbf];
                 if (q > 0) {
-                    cplx<T> t = tw[q * tk];
-                    t.y *= -s;   // table holds exp(-2 pi i j/n); sign s = -1 keeps it, +1 conjugates
+                    // exponent q k twstep < n; the LDS table holds exp(s 2 pi i j/n) for j < n/2
+                    const int jt = q * tk;
+                    const bool hi = jt >= half;
+                    cplx<T> t = tw[hi ? jt - half : jt];
+                    if (hi) { t.x = -t.x; t.y = -t.y; }
                     u = cmul<T>(u, t);
                 }
                 v[c][q] = u;
@@ -385,11 +389,12 @@ template <typename T>
 __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restrict__ pairs,
                                                           const int64_t *__restrict__ prefix, int npairs, int pass,
                                                           cplx<T> *__restrict__ ws, const cplx<T> *__restrict__ twtab,
-                                                          const double *__restrict__ precor, T s)
+                                                          const double *__restrict__ precor, int tw_off, T s)
 {
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *lds = reinterpret_cast<cplx<T> *>(smem_raw);
     __shared__ T lfac[kFftMaxLines];
+    __shared__ cplx<T> ltw[kFftMaxLen / 2];   // exp(s 2 pi i j/n), j < n/2
     const int p = (int)find_segment(prefix, npairs, blockIdx.x);
     const PairDev &P = pairs[p];
     const int64_t tile = (int64_t)blockIdx.x - prefix[p];
@@ -406,6 +411,15 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restr
     const int nl = (int)min((int64_t)L, lines - line0);
     const int half_in = nin / 2, half_n = n / 2;
 
+    {
+        // twiddles of this line length, staged with the data (sign s applied here)
+        const cplx<T> *tw = twtab + P.tw[pass];
+        for (int j = threadIdx.x; j < half_n; j += kFftThreads) {
+            cplx<T> t = tw[j];
+            t.y *= -s;   // table holds exp(-2 pi i j/n); s = -1 keeps it, +1 conjugates
+            ltw[j] = t;
+        }
+    }
     if (pass == 0) {
         if ((int)threadIdx.x < nl) {
             const int64_t li = line0 + threadIdx.x;
@@ -440,14 +454,13 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restr
         }
     }
     __syncthreads();
-    const cplx<T> *tw = twtab + P.tw[pass];
     int pc = 1;
     for (int st = 0; st < P.nrad[pass]; ++st) {
         const int R = P.radix[pass][st];
-        if (R == 4) fft_stage<T, 4>(lds, nl, n, pc, tw, s);
-        else if (R == 2) fft_stage<T, 2>(lds, nl, n, pc, tw, s);
-        else if (R == 3) fft_stage<T, 3>(lds, nl, n, pc, tw, s);
-        else fft_stage<T, 5>(lds, nl, n, pc, tw, s);
+        if (R == 4) fft_stage<T, 4>(lds, nl, n, pc, ltw, s);
+        else if (R == 2) fft_stage<T, 2>(lds, nl, n, pc, ltw, s);
+        else if (R == 3) fft_stage<T, 3>(lds, nl, n, pc, ltw, s);
+        else fft_stage<T, 5>(lds, nl, n, pc, ltw, s);
         pc *= R;
     }
     // kept window: wstart is 0 (whole line) or -R with 2R < n, so wstart + q lies in (-n, n)
@@ -804,12 +817,14 @@ hipError_t launch_spread(const PairDev *pairs, const int32_t *tile_pair, int64_t
 
 template <typename T>
 hipError_t launch_fft(const PairDev *pairs, const int64_t *prefix, int npairs, int64_t tiles, int pass, void *ws,
-                      const void *tw, const double *precor, int lds_elems, double sign, hipStream_t st)
+                      const void *tw, const double *precor, int lds_elems, int max_len, double sign, hipStream_t st)
 {
     if (tiles <= 0) return hipSuccess;
-    size_t lds = static_cast<size_t>(lds_elems) * sizeof(cplx<T>);
+    // dynamic LDS: the lines of one workgroup, then half a twiddle table of the longest line
+    size_t lds = static_cast<size_t>(lds_elems + max_len / 2) * sizeof(cplx<T>);
     hipLaunchKernelGGL(k_fft_pass<T>, dim3(static_cast<unsigned>(tiles)), dim3(kFftThreads), lds, st, pairs, prefix,
-                       npairs, pass, static_cast<cplx<T> *>(ws), static_cast<const cplx<T> *>(tw), precor, T(sign));
+                       npairs, pass, static_cast<cplx<T> *>(ws), static_cast<const cplx<T> *>(tw), precor, lds_elems,
+                       T(sign));
     return hipGetLastError();
 }
 
@@ -866,9 +881,9 @@ template hipError_t launch_spread<double>(const PairDev *, const int32_t *, int6
                                           const int64_t *, const int64_t *, const int32_t *, const double *, int64_t,
                                           const void *, void *, int, double, hipStream_t);
 template hipError_t launch_fft<float>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,
-                                      const double *, int, double, hipStream_t);
+                                      const double *, int, int, double, hipStream_t);
 template hipError_t launch_fft<double>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,
-                                       const double *, int, double, hipStream_t);
+                                       const double *, int, int, double, hipStream_t);
 template hipError_t launch_transpose<float>(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
 template hipError_t launch_transpose<double>(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
 template hipError_t launch_interp<float>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
