@@ -428,30 +428,59 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restr
         }
         __syncthreads();
     }
+    // every thread loads its (at most) kFftElems / kFftThreads elements into
+    // registers first, so the global loads are all in flight together, then
+    // writes them to LDS
+    constexpr int EPT = kFftElems / kFftThreads;
+    static_assert(kFftElems % kFftThreads == 0, "FFT workgroup elements");
+    const int ne = nl * n;
+    cplx<T> v[EPT];
     if (pass < 2) {
         const cplx<T> *sb = src + line0 * nin;
         const double *px = precor + P.precor[0] + half_in;
         const float rn = 1.0f / static_cast<float>(n);
-        for (int e = threadIdx.x; e < nl * n; e += kFftThreads) {
-            const int j = small_div(e, rn), f = e - __mul24(j, n);
-            const int l = f < half_n ? f : f - n;
-            cplx<T> v = mk<T>(T(0), T(0));
-            if (l >= -half_in && l < half_in) {
-                v = sb[__mul24(j, nin) + l + half_in];
-                if (pass == 0) v = cscale<T>(v, T(px[l]) * lfac[j]);
+        double fx[EPT];        // x pre-correction (pass x), applied after all loads are issued
+        int jl[EPT];
+#pragma unroll
+        for (int c = 0; c < EPT; ++c) {
+            const int e = threadIdx.x + c * kFftThreads;
+            v[c] = mk<T>(T(0), T(0));
+            fx[c] = 1.0;
+            jl[c] = 0;
+            if (e < ne) {
+                const int j = small_div(e, rn), f = e - __mul24(j, n);
+                const int l = f < half_n ? f : f - n;
+                jl[c] = j;
+                if (l >= -half_in && l < half_in) {
+                    v[c] = sb[__mul24(j, nin) + l + half_in];
+                    if (pass == 0) fx[c] = px[l];
+                }
             }
-            lds[e] = v;
+        }
+#pragma unroll
+        for (int c = 0; c < EPT; ++c) {
+            const int e = threadIdx.x + c * kFftThreads;
+            if (e < ne) lds[e] = pass == 0 ? cscale<T>(v[c], T(fx[c]) * lfac[jl[c]]) : v[c];
         }
     } else {
         const cplx<T> *sb = src + line0;
         const float rl = 1.0f / static_cast<float>(nl);
-        for (int e = threadIdx.x; e < nl * n; e += kFftThreads) {
-            const int f = small_div(e, rl), j = e - __mul24(f, nl);
-            const int l = f < half_n ? f : f - n;
-            cplx<T> v = mk<T>(T(0), T(0));
-            if (l >= -half_in && l < half_in) v = sb[(int64_t)(l + half_in) * lines + j];
-            lds[__mul24(j, n) + f] = v;
+        int slot[EPT];
+#pragma unroll
+        for (int c = 0; c < EPT; ++c) {
+            const int e = threadIdx.x + c * kFftThreads;
+            v[c] = mk<T>(T(0), T(0));
+            slot[c] = -1;
+            if (e < ne) {
+                const int f = small_div(e, rl), j = e - __mul24(f, nl);
+                const int l = f < half_n ? f : f - n;
+                slot[c] = __mul24(j, n) + f;
+                if (l >= -half_in && l < half_in) v[c] = sb[(int64_t)(l + half_in) * lines + j];
+            }
         }
+#pragma unroll
+        for (int c = 0; c < EPT; ++c)
+            if (slot[c] >= 0) lds[slot[c]] = v[c];
     }
     __syncthreads();
     int pc = 1;

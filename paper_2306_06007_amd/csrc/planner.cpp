@@ -498,10 +498,30 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
     for (auto &v : dp->alg_bytes) v = 0.0;
     for (auto &v : dp->alg_flops) v = 0.0;
 
+    // Direct sub-problems are evaluated as work items of <= kDirectTile targets x
+    // <= kDirectSeg sources.  Per target chunk, its direct source chunks are merged
+    // into contiguous source ranges (chunks are contiguous in chunk order), and
+    // consecutive target chunks with the same ranges share one target range, so
+    // items are cut from the merged rectangles rather than from every small pair.
+    std::vector<std::pair<int64_t, int64_t>> ranges, group_ranges;
+    int64_t group_t0 = 0, group_t1 = 0;
+    auto emit_group = [&]() {
+        for (int64_t t0 = group_t0; t0 < group_t1; t0 += kDirectTile)
+            for (const auto &r : group_ranges)
+                for (int64_t s0 = r.first; s0 < r.second; s0 += kDirectSeg) {
+                    DirectItem it;
+                    it.tgt_off = t0;
+                    it.src_off = s0;
+                    it.tgt_cnt = static_cast<int32_t>(std::min<int64_t>(kDirectTile, group_t1 - t0));
+                    it.src_cnt = static_cast<int32_t>(std::min<int64_t>(kDirectSeg, r.second - s0));
+                    dp->direct.push_back(it);
+                }
+    };
     for (int32_t j = 0; j < tgt.nc; ++j) {
         double S[3];
         for (int d = 0; d < 3; ++d) S[d] = std::max(tgt.half[3 * j + d], in.s_floor[d]);
         const int64_t nt = tgt.off[j + 1] - tgt.off[j];
+        ranges.clear();
         for (int32_t i = 0; i < src.nc; ++i) {
             const int64_t ns = src.off[i + 1] - src.off[i];
             PairGeom g = pair_geometry(&src.half[3 * i], S, p);
@@ -515,21 +535,25 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
             if (direct) {
                 dp->est_seconds += t_dir;
                 dp->direct_terms += static_cast<double>(ns) * nt;
-                for (int64_t t0 = 0; t0 < nt; t0 += kDirectTile)
-                    for (int64_t s0 = 0; s0 < ns; s0 += kDirectSeg) {
-                        DirectItem it;
-                        it.tgt_off = tgt.off[j] + t0;
-                        it.src_off = src.off[i] + s0;
-                        it.tgt_cnt = static_cast<int32_t>(std::min<int64_t>(kDirectTile, nt - t0));
-                        it.src_cnt = static_cast<int32_t>(std::min<int64_t>(kDirectSeg, ns - s0));
-                        dp->direct.push_back(it);
-                    }
+                if (ns == 0) continue;
+                if (!ranges.empty() && ranges.back().second == src.off[i]) ranges.back().second = src.off[i + 1];
+                else ranges.emplace_back(src.off[i], src.off[i + 1]);
             } else {
                 dp->est_seconds += t_nu;
                 nufft.push_back({i, j, g});
             }
         }
+        if (nt == 0) continue;
+        if (ranges == group_ranges && group_t1 == tgt.off[j]) {
+            group_t1 = tgt.off[j + 1];
+        } else {
+            emit_group();
+            group_ranges = ranges;
+            group_t0 = tgt.off[j];
+            group_t1 = tgt.off[j + 1];
+        }
     }
+    emit_group();
     dp->alg_flops[HVOX_K_DIRECT] = dp->direct_terms;
 
     // group NUFFT sub-problems into batches sharing the workspace

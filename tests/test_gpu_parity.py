@@ -247,3 +247,21 @@ def test_ska_like_full_size_sampled(dtype, eps):
     es, ea, info = both_directions(wl.uvw, wl.xyz, wl.sky, wl.vis, eps, dtype, rows_vis=rv, rows_pix=rp)
     _report(f"ska-like full {dtype} {eps:g}", es, ea, info)
     assert es <= eps and ea <= eps
+
+
+# ---- full-size LOFAR-like workload (5.0M x 4M, wide field), sampled rows -----------------
+@pytest.fixture(scope="module")
+def lofar_like():
+    return W.lofar_like()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
+def test_lofar_like_full_size_sampled(lofar_like, dtype, eps):
+    wl = lofar_like
+    rv = W.sample_rows(wl.n_vis, 256, seed=31)
+    rp = W.sample_rows(wl.n_pix, 256, seed=32)
+    es, ea, info = both_directions(wl.uvw, wl.xyz, wl.sky, wl.vis, eps, dtype, rows_vis=rv, rows_pix=rp)
+    _report(f"lofar-like full {dtype} {eps:g}", es, ea, info)
+    assert info["n_vis_chunks"] > 1 and info["n_sky_chunks"] > 1   # chunked evaluation
+    assert es <= eps and ea <= eps
