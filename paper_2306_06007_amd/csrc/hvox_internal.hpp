@@ -24,6 +24,9 @@ constexpr int kDirectSeg = 2048;     // sources per direct-sum work item
 constexpr int kInterpLanes = 16;     // interp: lanes per target
 constexpr int kInterpTargets = 256 / kInterpLanes;   // interp: targets per 256-thread workgroup
 constexpr int kMaxStages = 16;       // radix stages per FFT length
+// workgroups per launch of the kernels whose grid grows with the problem (direct,
+// interp): a dispatch counts its work-items in 32 bits
+constexpr int64_t kMaxLaunchBlocks = int64_t(1) << 22;
 // spreading gathers by grid-1 tile: one 256-thread workgroup per tile of
 // kTileX x kTileY x kTileZ cells, each thread owning one x-y column of kTileZ
 // cells; points touching the tile are staged kSpreadBatch at a time in LDS

@@ -16,6 +16,7 @@
 //  * accumulator: float64 complex per target (chunk order).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "hvox_internal.hpp"
@@ -591,17 +592,19 @@ __device__ __forceinline__ void cis_rev(double t, double &c, double &s)
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pairs, const int64_t *__restrict__ bprefix,
-                                                int npairs, const double *__restrict__ xyz, int64_t ntgt,
-                                                const double *__restrict__ deconv, const cplx<T> *__restrict__ ws,
-                                                double *__restrict__ acc, int w, T beta, double iota)
+                                                int npairs, int64_t block0, const double *__restrict__ xyz,
+                                                int64_t ntgt, const double *__restrict__ deconv,
+                                                const cplx<T> *__restrict__ ws, double *__restrict__ acc, int w,
+                                                T beta, double iota)
 {
     __shared__ T ker[kInterpTargets][3 * kWMax];
     const int sub = threadIdx.x & (kInterpLanes - 1), slot = threadIdx.x / kInterpLanes;
     const T two_over_w = T(2) / T(w);
     // every workgroup serves kInterpTargets consecutive targets of one sub-problem
-    const int p = (int)find_segment(bprefix, npairs, blockIdx.x);
+    const int64_t blk = block0 + blockIdx.x;
+    const int p = (int)find_segment(bprefix, npairs, blk);
     const PairDev &P = pairs[p];
-    const int64_t local = ((int64_t)blockIdx.x - bprefix[p]) * kInterpTargets + slot;
+    const int64_t local = (blk - bprefix[p]) * kInterpTargets + slot;
     const bool active = local < P.tgt_cnt;
     const int64_t k = P.tgt_off + (active ? local : 0);
     double s_k[3];
@@ -872,10 +875,14 @@ hipError_t launch_interp(const PairDev *pairs, const int64_t *bprefix, int npair
                          int64_t ntgt, const double *deconv, const void *ws, double *acc, int w, double beta,
                          double iota, hipStream_t st)
 {
-    if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_interp<T>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, pairs, bprefix, npairs,
-                       xyz, ntgt, deconv, static_cast<const cplx<T> *>(ws), acc, w, T(beta), iota);
-    return hipGetLastError();
+    for (int64_t b0 = 0; b0 < blocks; b0 += kMaxLaunchBlocks) {
+        const int64_t nb = std::min<int64_t>(kMaxLaunchBlocks, blocks - b0);
+        hipLaunchKernelGGL(k_interp<T>, dim3(static_cast<unsigned>(nb)), dim3(256), 0, st, pairs, bprefix, npairs, b0,
+                           xyz, ntgt, deconv, static_cast<const cplx<T> *>(ws), acc, w, T(beta), iota);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename T>
@@ -883,10 +890,16 @@ hipError_t launch_direct(const DirectItem *items, int64_t nitems, const double *
                          const double *txyz, int64_t ntgt, const int32_t *perm, const void *in, double *acc,
                          double iota, hipStream_t st)
 {
-    if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_direct<T>, dim3(static_cast<unsigned>(nitems)), dim3(kDirectThreads), 0, st, items, sxyz,
-                       nsrc, txyz, ntgt, perm, static_cast<const cplx<T> *>(in), acc, iota);
-    return hipGetLastError();
+    // one workgroup per item, in launches of at most kMaxLaunchBlocks workgroups
+    // (a dispatch counts its work-items in 32 bits)
+    for (int64_t i0 = 0; i0 < nitems; i0 += kMaxLaunchBlocks) {
+        const int64_t nb = std::min<int64_t>(kMaxLaunchBlocks, nitems - i0);
+        hipLaunchKernelGGL(k_direct<T>, dim3(static_cast<unsigned>(nb)), dim3(kDirectThreads), 0, st, items + i0,
+                           sxyz, nsrc, txyz, ntgt, perm, static_cast<const cplx<T> *>(in), acc, iota);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename T>
