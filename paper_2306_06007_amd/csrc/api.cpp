@@ -40,7 +40,7 @@ hipError_t launch_interp(const PairDev *, const int64_t *, int, int64_t, const d
                          const void *, double *, int, double, double, hipStream_t);
 template <typename T>
 hipError_t launch_direct(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
-                         const int32_t *, const void *, double *, double, hipStream_t);
+                         const int32_t *, const void *, int64_t, double *, int64_t, int, double, hipStream_t);
 template <typename T>
 hipError_t launch_finalize(const double *, int64_t, const int32_t *, void *, int, hipStream_t);
 
@@ -220,63 +220,76 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
         if (e != hipSuccess) return fail(HVOX_ERR_HIP, std::string("HIP: ") + hipGetErrorString(e)); \
     } while (0)
 
-    for (int32_t t = 0; t < ntrans; ++t) {
-        const C *in_t = static_cast<const C *>(in) + static_cast<int64_t>(t) * n_src;
-        C *out_t = static_cast<C *>(out) + static_cast<int64_t>(t) * n_tgt;
+    // rows in groups of up to kRowBatch: the NUFFT sub-problems run row by row
+    // into the group's accumulator rows, the direct sum covers all rows of the
+    // group in one launch (its phase factors are shared by the rows)
+    for (int32_t t0 = 0; t0 < ntrans; t0 += kRowBatch) {
+        const int nb = static_cast<int>(std::min<int32_t>(kRowBatch, ntrans - t0));
         if (n_tgt == 0) continue;
-        HVOX_TRY(timed(pl, HVOX_K_ZERO, st, [&] { return launch_zero(pl->acc, 2 * n_tgt, st); }));
-        for (const Batch &b : dp.batches) {
-            const PairDev *pairs = dd.pairs + b.pair0;
-            const int np = static_cast<int>(b.npairs);
-            const int64_t *pprefix = dd.pre_pts + b.pre_pts;
-            const int64_t tile_base = dp.pairs[b.pair0].tile0;
-            HVOX_TRY(timed(pl, HVOX_K_PREPHASE, st, [&] {
-                return launch_prephase<T>(pairs, pprefix, np, b.pts, sxyz, n_src, sperm, in_t, pl->stage, iota, st);
-            }));
-            if (b.sparse) {
-                // mostly empty grid 1: clear the batch's grid-1 region, then spread the listed tiles
-                HVOX_TRY(timed(pl, HVOX_K_ZERO, st, [&] {
-                    return launch_zero(static_cast<double *>(pl->ws),
-                                       b.g_cnt * static_cast<int64_t>(sizeof(C) / sizeof(double)), st);
+        HVOX_TRY(timed(pl, HVOX_K_ZERO, st, [&] { return launch_zero(pl->acc, 2 * n_tgt * nb, st); }));
+        for (int r = 0; r < nb; ++r) {
+            const C *in_t = static_cast<const C *>(in) + static_cast<int64_t>(t0 + r) * n_src;
+            double *acc_r = pl->acc + 2 * n_tgt * r;
+            for (const Batch &b : dp.batches) {
+                const PairDev *pairs = dd.pairs + b.pair0;
+                const int np = static_cast<int>(b.npairs);
+                const int64_t *pprefix = dd.pre_pts + b.pre_pts;
+                const int64_t tile_base = dp.pairs[b.pair0].tile0;
+                HVOX_TRY(timed(pl, HVOX_K_PREPHASE, st, [&] {
+                    return launch_prephase<T>(pairs, pprefix, np, b.pts, sxyz, n_src, sperm, in_t, pl->stage, iota,
+                                              st);
                 }));
-                HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
-                    return launch_spread<T>(pairs, dd.tile_pair, tile_base, pprefix, b.list_cnt,
-                                            dd.tile_list + b.list_off, dd.tile_off, dd.records, sxyz, n_src,
-                                            pl->stage, pl->ws, p.w, p.beta, st);
-                }));
-            } else {
-                HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
-                    return launch_spread<T>(pairs, dd.tile_pair, tile_base, pprefix, b.stiles, nullptr, dd.tile_off,
-                                            dd.records, sxyz, n_src, pl->stage, pl->ws, p.w, p.beta, st);
-                }));
-            }
-            for (int pass = 0; pass < 3; ++pass) {
-                HVOX_TRY(timed(pl, HVOX_K_FFT_X + pass, st, [&] {
-                    return launch_fft<T>(pairs, dd.pre_tiles[pass] + b.pre_tiles[pass], np, b.tiles[pass], pass,
-                                         pl->ws, pl->tw, pl->precor, b.lds_elems[pass], b.max_pass_len[pass], iota,
-                                         st);
-                }));
-                if (pass == 0)
-                    HVOX_TRY(timed(pl, HVOX_K_TRANSPOSE, st, [&] {
-                        return launch_transpose<T>(pairs, dd.pre_ttiles + b.pre_ttiles, np, b.ttiles, pl->ws, st);
+                if (b.sparse) {
+                    // mostly empty grid 1: clear the batch's grid-1 region, then spread the listed tiles
+                    HVOX_TRY(timed(pl, HVOX_K_ZERO, st, [&] {
+                        return launch_zero(static_cast<double *>(pl->ws),
+                                           b.g_cnt * static_cast<int64_t>(sizeof(C) / sizeof(double)), st);
                     }));
+                    HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
+                        return launch_spread<T>(pairs, dd.tile_pair, tile_base, pprefix, b.list_cnt,
+                                                dd.tile_list + b.list_off, dd.tile_off, dd.records, sxyz, n_src,
+                                                pl->stage, pl->ws, p.w, p.beta, st);
+                    }));
+                } else {
+                    HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
+                        return launch_spread<T>(pairs, dd.tile_pair, tile_base, pprefix, b.stiles, nullptr,
+                                                dd.tile_off, dd.records, sxyz, n_src, pl->stage, pl->ws, p.w, p.beta,
+                                                st);
+                    }));
+                }
+                for (int pass = 0; pass < 3; ++pass) {
+                    HVOX_TRY(timed(pl, HVOX_K_FFT_X + pass, st, [&] {
+                        return launch_fft<T>(pairs, dd.pre_tiles[pass] + b.pre_tiles[pass], np, b.tiles[pass], pass,
+                                             pl->ws, pl->tw, pl->precor, b.lds_elems[pass], b.max_pass_len[pass],
+                                             iota, st);
+                    }));
+                    if (pass == 0)
+                        HVOX_TRY(timed(pl, HVOX_K_TRANSPOSE, st, [&] {
+                            return launch_transpose<T>(pairs, dd.pre_ttiles + b.pre_ttiles, np, b.ttiles, pl->ws,
+                                                       st);
+                        }));
+                }
+                HVOX_TRY(timed(pl, HVOX_K_INTERP, st, [&] {
+                    return launch_interp<T>(pairs, dd.pre_tgts + b.pre_tgts, np, b.iblocks, txyz, n_tgt, dd.deconv,
+                                            pl->ws, acc_r, p.w2, p.beta2, iota, st);
+                }));
             }
-            HVOX_TRY(timed(pl, HVOX_K_INTERP, st, [&] {
-                return launch_interp<T>(pairs, dd.pre_tgts + b.pre_tgts, np, b.iblocks, txyz, n_tgt, dd.deconv, pl->ws,
-                                        pl->acc, p.w2, p.beta2, iota, st);
-            }));
         }
         if (!dp.direct.empty())
             HVOX_TRY(timed(pl, HVOX_K_DIRECT, st, [&] {
                 return launch_direct<T>(dd.direct, static_cast<int64_t>(dp.direct.size()), sxyz, n_src, txyz, n_tgt,
-                                        sperm, in_t, pl->acc, iota, st);
+                                        sperm, static_cast<const C *>(in) + static_cast<int64_t>(t0) * n_src, n_src,
+                                        pl->acc, 2 * n_tgt, nb, iota, st);
             }));
-        HVOX_TRY(timed(pl, HVOX_K_FINAL, st, [&] {
-            return launch_finalize<T>(pl->acc, n_tgt, tperm, out_t, real_only, st);
-        }));
+        for (int r = 0; r < nb; ++r) {
+            C *out_t = static_cast<C *>(out) + static_cast<int64_t>(t0 + r) * n_tgt;
+            HVOX_TRY(timed(pl, HVOX_K_FINAL, st, [&] {
+                return launch_finalize<T>(pl->acc + 2 * n_tgt * r, n_tgt, tperm, out_t, real_only, st);
+            }));
+        }
         for (int k = 0; k < HVOX_K_COUNT; ++k) {
-            pl->stats.alg_bytes[k] += dp.alg_bytes[k];
-            pl->stats.alg_flops[k] += dp.alg_flops[k];
+            pl->stats.alg_bytes[k] += dp.alg_bytes[k] * nb;
+            pl->stats.alg_flops[k] += dp.alg_flops[k] * nb;
         }
     }
 #undef HVOX_TRY
@@ -496,7 +509,9 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
         "deconvolution kernel");
     // accumulator and workspace
     const size_t delta = p.dtype == HVOX_F64 ? 16 : 8;
-    chk(dev_alloc(pl, 16 * static_cast<size_t>(std::max(hp.n_vis, hp.n_pix)), &tmp, true), "accumulator");
+    chk(dev_alloc(pl, 16 * static_cast<size_t>(kRowBatch) * static_cast<size_t>(std::max(hp.n_vis, hp.n_pix)), &tmp,
+                  true),
+        "accumulator");
     pl->acc = static_cast<double *>(tmp);
     chk(dev_alloc(pl, delta * static_cast<size_t>(hp.ws_elems), &pl->ws, false), "workspace");
     int64_t max_pts = 0;
@@ -685,7 +700,7 @@ int hvox_plan_info(hvox_plan_t plan, hvox_plan_info_t *out)
     out->max_pair_workspace_bytes = hp.max_pair_ws * delta;
     if (plan->host_only) {
         int64_t r = 16 * (hp.n_vis + hp.n_pix) + 4 * (hp.n_vis + hp.n_pix) + 8 * (hp.n_vis + hp.n_pix) +
-                    16 * std::max(hp.n_vis, hp.n_pix);
+                    16 * kRowBatch * std::max(hp.n_vis, hp.n_pix);
         r += static_cast<int64_t>((hp.syn.pairs.size() + hp.ana.pairs.size()) * sizeof(PairDev));
         r += static_cast<int64_t>((hp.syn.direct.size() + hp.ana.direct.size()) * sizeof(DirectItem));
         out->resident_bytes = r;

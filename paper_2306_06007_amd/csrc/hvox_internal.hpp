@@ -21,6 +21,7 @@ constexpr int kDirectThreads = 256;  // threads of a direct-sum workgroup
 constexpr int kDirectTile = 512;     // targets per direct-sum workgroup (two per thread)
 constexpr int kDirectSrcTile = 256;  // sources staged in LDS at a time
 constexpr int kDirectSeg = 2048;     // sources per direct-sum work item
+constexpr int kRowBatch = 4;         // data rows (ntrans) per direct-sum launch and accumulator rows
 constexpr int kInterpLanes = 16;     // interp: lanes per target
 constexpr int kInterpTargets = 256 / kInterpLanes;   // interp: targets per 256-thread workgroup
 constexpr int kMaxStages = 16;       // radix stages per FFT length

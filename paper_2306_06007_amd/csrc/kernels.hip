@@ -679,7 +679,8 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
 // direct evaluation of a sub-problem block (Sect. 3.1, last bullet; the
 // eps = 0 mode of Sect. 4):  f_k += sum_n c_n exp(2 pi i iota s_k.x_n).
 // A workgroup of 256 threads owns <= 512 targets (two per thread) and
-// <= kDirectSeg sources, staged 256 at a time in LDS.  Per source tile with reference
+// <= kDirectSeg sources, staged 256 at a time in LDS, for NT data rows at
+// once (the phase factors are computed once and applied to every row).  Per source tile with reference
 // point x_S and target-tile reference s_T,
 //   s_k.x_n = s_k.x_S + s_T.(x_n - x_S) + (s_k - s_T).(x_n - x_S):
 // the first two terms are evaluated once per (target, tile) and
@@ -689,17 +690,17 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
 // accumulates c exp(+2 pi i t).  Phases are float64 (full rate on CDNA).
 // ---------------------------------------------------------------------------
 
-template <typename T>
+template <typename T, int NT>
 __global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__restrict__ items,
                                                            const double *__restrict__ sxyz, int64_t nsrc,
                                                            const double *__restrict__ txyz, int64_t ntgt,
                                                            const int32_t *__restrict__ perm,
-                                                           const cplx<T> *__restrict__ in, double *__restrict__ acc,
-                                                           double iota)
+                                                           const cplx<T> *__restrict__ in, int64_t in_stride,
+                                                           double *__restrict__ acc, int64_t acc_stride, double iota)
 {
     static_assert(kDirectSrcTile == kDirectThreads && kDirectTile == 2 * kDirectThreads, "direct tiling");
     __shared__ double lx[kDirectSrcTile], ly[kDirectSrcTile], lz[kDirectSrcTile];
-    __shared__ cplx<T> lc[kDirectSrcTile];
+    __shared__ cplx<T> lc[NT][kDirectSrcTile];
     const DirectItem it = items[blockIdx.x];
     const int tid = threadIdx.x;
     // two targets per thread: each staged source is read from LDS once for both
@@ -714,7 +715,9 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__r
         sp0[d] = iota * (sk0[d] - sT[d]);        // the sign enters through the phase
         sp1[d] = iota * (sk1[d] - sT[d]);
     }
-    double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
+    double a0r[NT], a0i[NT], a1r[NT], a1i[NT];
+#pragma unroll
+    for (int r = 0; r < NT; ++r) a0r[r] = a0i[r] = a1r[r] = a1i[r] = 0.0;
     for (int s0 = 0; s0 < it.src_cnt; s0 += kDirectSrcTile) {
         const int64_t nS = it.src_off + s0;
         double xS[3];
@@ -733,23 +736,33 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__r
             ly[tid] = dxv[1];
             lz[tid] = dxv[2];
             const double2 e = cis_cycles(ph, iota);
-            const cplx<T> c = in[perm[n]];
-            lc[tid] = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
+            const int64_t u = perm[n];
+#pragma unroll
+            for (int r = 0; r < NT; ++r) {
+                const cplx<T> c = in[r * in_stride + u];
+                lc[r][tid] = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
+            }
         }
         __syncthreads();
-        T b0r = T(0), b0i = T(0), b1r = T(0), b1i = T(0);
+        T b0r[NT], b0i[NT], b1r[NT], b1i[NT];
+#pragma unroll
+        for (int r = 0; r < NT; ++r) b0r[r] = b0i[r] = b1r[r] = b1i[r] = T(0);
         for (int j = 0; j < cnt; ++j) {
             const double xj = lx[j], yj = ly[j], zj = lz[j];
-            const cplx<T> c = lc[j];
             const double t0 = fma(sp0[0], xj, fma(sp0[1], yj, sp0[2] * zj));
             const double t1 = fma(sp1[0], xj, fma(sp1[1], yj, sp1[2] * zj));
             T c0, s0v, c1, s1v;
             cis_rev(t0, c0, s0v);
             cis_rev(t1, c1, s1v);
-            b0r = fma(c.x, c0, fma(-c.y, s0v, b0r));
-            b0i = fma(c.x, s0v, fma(c.y, c0, b0i));
-            b1r = fma(c.x, c1, fma(-c.y, s1v, b1r));
-            b1i = fma(c.x, s1v, fma(c.y, c1, b1i));
+            // one phase factor per (target, source), applied to every row
+#pragma unroll
+            for (int r = 0; r < NT; ++r) {
+                const cplx<T> c = lc[r][j];
+                b0r[r] = fma(c.x, c0, fma(-c.y, s0v, b0r[r]));
+                b0i[r] = fma(c.x, s0v, fma(c.y, c0, b0i[r]));
+                b1r[r] = fma(c.x, c1, fma(-c.y, s1v, b1r[r]));
+                b1i[r] = fma(c.x, s1v, fma(c.y, c1, b1i[r]));
+            }
         }
         double ph0 = 0.0, ph1 = 0.0;
         for (int d = 0; d < 3; ++d) {
@@ -757,18 +770,25 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__r
             ph1 += sk1[d] * xS[d];
         }
         const double2 e0 = cis_cycles(ph0, iota), e1 = cis_cycles(ph1, iota);
-        a0r += (double)b0r * e0.x - (double)b0i * e0.y;
-        a0i += (double)b0r * e0.y + (double)b0i * e0.x;
-        a1r += (double)b1r * e1.x - (double)b1i * e1.y;
-        a1i += (double)b1r * e1.y + (double)b1i * e1.x;
+#pragma unroll
+        for (int r = 0; r < NT; ++r) {
+            a0r[r] += (double)b0r[r] * e0.x - (double)b0i[r] * e0.y;
+            a0i[r] += (double)b0r[r] * e0.y + (double)b0i[r] * e0.x;
+            a1r[r] += (double)b1r[r] * e1.x - (double)b1i[r] * e1.y;
+            a1i[r] += (double)b1r[r] * e1.y + (double)b1i[r] * e1.x;
+        }
     }
-    if (has0) {
-        atomicAdd(acc + 2 * k0, a0r);
-        atomicAdd(acc + 2 * k0 + 1, a0i);
-    }
-    if (has1) {
-        atomicAdd(acc + 2 * k1, a1r);
-        atomicAdd(acc + 2 * k1 + 1, a1i);
+#pragma unroll
+    for (int r = 0; r < NT; ++r) {
+        double *ar = acc + r * acc_stride;
+        if (has0) {
+            atomicAdd(ar + 2 * k0, a0r[r]);
+            atomicAdd(ar + 2 * k0 + 1, a0i[r]);
+        }
+        if (has1) {
+            atomicAdd(ar + 2 * k1, a1r[r]);
+            atomicAdd(ar + 2 * k1 + 1, a1i[r]);
+        }
     }
 }
 
@@ -885,21 +905,41 @@ hipError_t launch_interp(const PairDev *pairs, const int64_t *bprefix, int npair
     return hipSuccess;
 }
 
-template <typename T>
-hipError_t launch_direct(const DirectItem *items, int64_t nitems, const double *sxyz, int64_t nsrc,
-                         const double *txyz, int64_t ntgt, const int32_t *perm, const void *in, double *acc,
-                         double iota, hipStream_t st)
+template <typename T, int NT>
+static hipError_t launch_direct_rows(const DirectItem *items, int64_t nitems, const double *sxyz, int64_t nsrc,
+                                     const double *txyz, int64_t ntgt, const int32_t *perm, const void *in,
+                                     int64_t in_stride, double *acc, int64_t acc_stride, double iota, hipStream_t st)
 {
     // one workgroup per item, in launches of at most kMaxLaunchBlocks workgroups
     // (a dispatch counts its work-items in 32 bits)
     for (int64_t i0 = 0; i0 < nitems; i0 += kMaxLaunchBlocks) {
         const int64_t nb = std::min<int64_t>(kMaxLaunchBlocks, nitems - i0);
-        hipLaunchKernelGGL(k_direct<T>, dim3(static_cast<unsigned>(nb)), dim3(kDirectThreads), 0, st, items + i0,
-                           sxyz, nsrc, txyz, ntgt, perm, static_cast<const cplx<T> *>(in), acc, iota);
+        hipLaunchKernelGGL((k_direct<T, NT>), dim3(static_cast<unsigned>(nb)), dim3(kDirectThreads), 0, st,
+                           items + i0, sxyz, nsrc, txyz, ntgt, perm, static_cast<const cplx<T> *>(in), in_stride, acc,
+                           acc_stride, iota);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_direct(const DirectItem *items, int64_t nitems, const double *sxyz, int64_t nsrc,
+                         const double *txyz, int64_t ntgt, const int32_t *perm, const void *in, int64_t in_stride,
+                         double *acc, int64_t acc_stride, int rows, double iota, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    switch (rows) {
+    case 1: return launch_direct_rows<T, 1>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
+                                            acc_stride, iota, st);
+    case 2: return launch_direct_rows<T, 2>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
+                                            acc_stride, iota, st);
+    case 3: return launch_direct_rows<T, 3>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
+                                            acc_stride, iota, st);
+    case 4: return launch_direct_rows<T, 4>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
+                                            acc_stride, iota, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T>
@@ -932,10 +972,12 @@ template hipError_t launch_interp<float>(const PairDev *, const int64_t *, int, 
                                          const double *, const void *, double *, int, double, double, hipStream_t);
 template hipError_t launch_interp<double>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
                                           const double *, const void *, double *, int, double, double, hipStream_t);
-template hipError_t launch_direct<float>(const DirectItem *, int64_t, const double *, int64_t, const double *,
-                                         int64_t, const int32_t *, const void *, double *, double, hipStream_t);
-template hipError_t launch_direct<double>(const DirectItem *, int64_t, const double *, int64_t, const double *,
-                                          int64_t, const int32_t *, const void *, double *, double, hipStream_t);
+template hipError_t launch_direct<float>(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
+                                         const int32_t *, const void *, int64_t, double *, int64_t, int, double,
+                                         hipStream_t);
+template hipError_t launch_direct<double>(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
+                                          const int32_t *, const void *, int64_t, double *, int64_t, int, double,
+                                          hipStream_t);
 template hipError_t launch_finalize<float>(const double *, int64_t, const int32_t *, void *, int, hipStream_t);
 template hipError_t launch_finalize<double>(const double *, int64_t, const int32_t *, void *, int, hipStream_t);
 

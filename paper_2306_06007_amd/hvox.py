@@ -357,9 +357,10 @@ class Plan:
 def footprint_bound(n_vis: int, n_pix: int, dtype: str, workspace_bytes: float) -> float:
     """Upper bound on a plan's device memory before planning: coordinates,
     permutations, deconvolution factors and accumulator per point, the
-    workspace cap, and sub-problem tables (bounded generously)."""
+    workspace cap, and sub-problem tables (bounded generously).  The
+    accumulator holds four rows (the direct sum's row batch)."""
     per_point = 24 + 4 + 8 + 16
-    return float(per_point * (n_vis + n_pix) + 16 * max(n_vis, n_pix) + workspace_bytes + 64e6)
+    return float(per_point * (n_vis + n_pix) + 16 * 4 * max(n_vis, n_pix) + workspace_bytes + 64e6)
 
 
 def rel_l2(y, ref) -> float:
