@@ -31,7 +31,7 @@ hipError_t launch_spread(const PairDev *, const int32_t *, int64_t, const int64_
                          const int64_t *, const int32_t *, const double *, int64_t, const void *, void *, int, double,
                          hipStream_t);
 template <typename T>
-hipError_t launch_fft(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *, const double *, int,
+hipError_t launch_fft(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *, const void *, int,
                       int, double, hipStream_t);
 template <typename T>
 hipError_t launch_transpose(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
@@ -83,7 +83,7 @@ struct hvox_plan_s {
     std::vector<void *> allocations;
     double *vis_xyz = nullptr, *sky_xyz = nullptr;     // SoA [3][n], chunk order
     int32_t *vis_perm = nullptr, *sky_perm = nullptr;
-    double *precor = nullptr;
+    void *precor = nullptr;                             // pre-correction tables in the plan's precision
     void *tw = nullptr;
     hvox::DevDir syn, ana;
     void *ws = nullptr;
@@ -449,7 +449,17 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
         for (int q = 0; q < nq; ++q) s += aq2[q] * std::cos(M_PI * hp.precor_nu[i] * p.w2 * zq[q]);
         precor[i] = 1.0 / (0.5 * p.w2 * s);
     }
-    chk(upload(pl, precor, &pl->precor, st), "pre-correction tables");
+    if (p.dtype == HVOX_F64) {
+        double *d = nullptr;
+        chk(upload(pl, precor, &d, st), "pre-correction tables");
+        pl->precor = d;
+    } else {
+        std::vector<float> precor32(precor.begin(), precor.end());
+        float *d = nullptr;
+        chk(upload(pl, precor32, &d, st), "pre-correction tables");
+        chk(hipStreamSynchronize(st), "pre-correction upload");   // precor32 is released on return
+        pl->precor = d;
+    }
     // twiddles exp(-2 pi i j / n); the host tables stay alive until the
     // stream synchronisation that ends the plan upload
     std::vector<double2> tw64;
@@ -783,7 +793,7 @@ extern "C" int hvox_test_fft(int32_t dtype, int32_t n, int32_t nin, int32_t nlin
     pd.wstart[0] = wstart; pd.wcount[0] = wcount;
     pd.wstart[1] = 0; pd.wcount[1] = nlines; pd.wstart[2] = 0; pd.wcount[2] = 1;
     pd.nrad[0] = factor_radices(n, pd.radix[0]);
-    pd.lines_per_tile[0] = std::max(1, std::min(kFftMaxLines, kFftElems / n));
+    pd.lines_per_tile[0] = fft_lines(n);
     const int64_t lines = nlines;
     const int64_t tiles = (lines + pd.lines_per_tile[0] - 1) / pd.lines_per_tile[0];
     const int64_t gin = static_cast<int64_t>(nin) * nlines, gout = static_cast<int64_t>(wcount) * nlines;
@@ -793,6 +803,7 @@ extern "C" int hvox_test_fft(int32_t dtype, int32_t n, int32_t nin, int32_t nlin
     pd.precor[0] = 0; pd.precor[1] = nin; pd.precor[2] = nin + nlines;
     pd.tw[0] = 0;
     std::vector<double> ones(nin + nlines + 1, 1.0);
+    std::vector<float> ones32(nin + nlines + 1, 1.0f);
     std::vector<double2> tw64(n);
     std::vector<float2> tw32(n);
     for (int j = 0; j < n; ++j) {
@@ -809,7 +820,7 @@ extern "C" int hvox_test_fft(int32_t dtype, int32_t n, int32_t nin, int32_t nlin
     if (e == hipSuccess) e = hipMalloc(&d_tw, delta * n);
     if (e == hipSuccess) e = hipMalloc(&d_pd, sizeof(PairDev));
     if (e == hipSuccess) e = hipMalloc(&d_pre, sizeof(int64_t) * 2);
-    if (e == hipSuccess) e = hipMalloc(&d_one, sizeof(double) * ones.size());
+    if (e == hipSuccess) e = hipMalloc(&d_one, delta / 2 * ones.size());
     if (e == hipSuccess) e = hipMemcpyAsync(d_ws, in, delta * gin, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_tw, dtype == HVOX_F64 ? static_cast<const void *>(tw64.data()) : tw32.data(), delta * n,
@@ -817,14 +828,15 @@ extern "C" int hvox_test_fft(int32_t dtype, int32_t n, int32_t nin, int32_t nlin
     if (e == hipSuccess) e = hipMemcpyAsync(d_pd, &pd, sizeof(PairDev), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(d_pre, prefix.data(), sizeof(int64_t) * 2, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(d_one, ones.data(), sizeof(double) * ones.size(), hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(d_one, dtype == HVOX_F64 ? static_cast<const void *>(ones.data()) : ones32.data(),
+                           delta / 2 * ones.size(), hipMemcpyHostToDevice, st);
     const int lds = pd.lines_per_tile[0] * n;
     if (e == hipSuccess)
         e = dtype == HVOX_F64
                 ? launch_fft<double>(static_cast<PairDev *>(d_pd), static_cast<int64_t *>(d_pre), 1, tiles, 0, d_ws,
-                                     d_tw, static_cast<double *>(d_one), lds, n, sign, st)
+                                     d_tw, d_one, lds, n, sign, st)
                 : launch_fft<float>(static_cast<PairDev *>(d_pd), static_cast<int64_t *>(d_pre), 1, tiles, 0, d_ws,
-                                    d_tw, static_cast<double *>(d_one), lds, n, sign, st);
+                                    d_tw, d_one, lds, n, sign, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(out, static_cast<char *>(d_ws) + delta * gin, delta * gout, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);

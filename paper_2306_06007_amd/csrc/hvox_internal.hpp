@@ -12,15 +12,26 @@ namespace hvox {
 
 // ---- compile-time limits -------------------------------------------------
 constexpr int kWMax = 24;            // largest kernel support handled by the kernels
-constexpr int kFftThreads = 512;     // threads of one FFT workgroup
+constexpr int kFftThreads = 512;     // threads of an FFT workgroup for lines longer than kFftSmallLen
+constexpr int kFftThreadsSmall = 256;   // threads of an FFT workgroup when every line is <= kFftSmallLen
+constexpr int kFftSmallLen = 2048;
 constexpr int kTransposeTile = 32;   // square tile of the transpose kernel
-constexpr int kFftElems = 4096;      // complex elements (lines x length) held in LDS by one workgroup
+constexpr int kFftElems = 4096;      // complex elements (lines x length) held in LDS by one workgroup (at most)
+// elements of a workgroup of nt threads (eight per thread), and the workgroup
+// size and lines per workgroup used for an FFT length n
+constexpr int fft_elems(int nt) { return 8 * nt; }
+constexpr int fft_threads(int n) { return n <= kFftSmallLen ? kFftThreadsSmall : kFftThreads; }
 constexpr int kFftMaxLen = 4096;     // longest 1D FFT (one line must fit a workgroup)
 constexpr int kFftMaxLines = 64;     // lines per FFT workgroup
+constexpr int fft_lines(int n)
+{
+    return n >= fft_elems(fft_threads(n)) ? 1 : (fft_elems(fft_threads(n)) / n < kFftMaxLines ? fft_elems(fft_threads(n)) / n : kFftMaxLines);
+}
 constexpr int kDirectThreads = 256;  // threads of a direct-sum workgroup
 constexpr int kDirectTile = 512;     // targets per direct-sum workgroup (two per thread)
 constexpr int kDirectSrcTile = 256;  // sources staged in LDS at a time
-constexpr int kDirectSeg = 2048;     // sources per direct-sum work item
+constexpr int kDirectSeg = 8192;     // longest source segment of a direct-sum work item
+constexpr int64_t kDirectMinItems = 4096;   // shorter segments while a plan has fewer direct work items
 constexpr int kRowBatch = 4;         // data rows (ntrans) per direct-sum launch and accumulator rows
 constexpr int kInterpLanes = 16;     // interp: lanes per target
 constexpr int kInterpTargets = 256 / kInterpLanes;   // interp: targets per 256-thread workgroup

@@ -328,10 +328,10 @@ __device__ __forceinline__ void dft_small(cplx<T> *u, T s)
 // registers, then (after a barrier) writes them back in autosorted order.
 // Butterfly i of a line: k = i mod p, inputs x[i + q n/R] twiddled by
 // w^(k q n / (p R)), outputs at (i - k) R + k + m p.
-template <typename T, int R>
+template <typename T, int R, int NT>
 __device__ void fft_stage(cplx<T> *lds, int nl, int n, int p, const cplx<T> *tw, T s)
 {
-    constexpr int MAXB = (kFftElems / R + kFftThreads - 1) / kFftThreads;
+    constexpr int MAXB = (fft_elems(NT) / R + NT - 1) / NT;
     const int nbf = n / R;
     const int total = nl * nbf;
     const int twstep = n / (p * R);
@@ -341,7 +341,7 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int p, const cplx<T> *tw,
     int obase[MAXB];
 #pragma unroll
     for (int c = 0; c < MAXB; ++c) {
-        const int b = threadIdx.x + c * kFftThreads;
+        const int b = threadIdx.x + c * NT;
         obase[c] = -1;
         if (b < total) {
             const int j = small_div(b, rnbf), i = b - __mul24(j, nbf);
@@ -386,16 +386,16 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int p, const cplx<T> *tw,
 // 1/Phi_hat(l/n2) of all three axes (the (y, z) factor once per line).  Output
 // q of the kept window is FFT index (wstart + q) mod n, written line-major:
 // out[line][q].
-template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restrict__ pairs,
-                                                          const int64_t *__restrict__ prefix, int npairs, int pass,
-                                                          cplx<T> *__restrict__ ws, const cplx<T> *__restrict__ twtab,
-                                                          const double *__restrict__ precor, int tw_off, T s)
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pairs, const int64_t *__restrict__ prefix,
+                                                 int npairs, int pass, cplx<T> *__restrict__ ws,
+                                                 const cplx<T> *__restrict__ twtab, const T *__restrict__ precor,
+                                                 int tw_off, T s)
 {
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *lds = reinterpret_cast<cplx<T> *>(smem_raw);
+    cplx<T> *ltw = lds + tw_off;              // exp(s 2 pi i j/n), j < n/2, after the lines
     __shared__ T lfac[kFftMaxLines];
-    __shared__ cplx<T> ltw[kFftMaxLen / 2];   // exp(s 2 pi i j/n), j < n/2
     const int p = (int)find_segment(prefix, npairs, blockIdx.x);
     const PairDev &P = pairs[p];
     const int64_t tile = (int64_t)blockIdx.x - prefix[p];
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restr
     {
         // twiddles of this line length, staged with the data (sign s applied here)
         const cplx<T> *tw = twtab + P.tw[pass];
-        for (int j = threadIdx.x; j < half_n; j += kFftThreads) {
+        for (int j = threadIdx.x; j < half_n; j += NT) {
             cplx<T> t = tw[j];
             t.y *= -s;   // table holds exp(-2 pi i j/n); s = -1 keeps it, +1 conjugates
             ltw[j] = t;
@@ -425,28 +425,28 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restr
         if ((int)threadIdx.x < nl) {
             const int64_t li = line0 + threadIdx.x;
             const int64_t lz = li / P.n1[1], ly = li - lz * P.n1[1];
-            lfac[threadIdx.x] = T(precor[P.precor[1] + ly] * precor[P.precor[2] + lz]);
+            lfac[threadIdx.x] = precor[P.precor[1] + ly] * precor[P.precor[2] + lz];
         }
         __syncthreads();
     }
-    // every thread loads its (at most) kFftElems / kFftThreads elements into
+    // every thread loads its (at most) fft_elems(NT) / NT elements into
     // registers first, so the global loads are all in flight together, then
     // writes them to LDS
-    constexpr int EPT = kFftElems / kFftThreads;
-    static_assert(kFftElems % kFftThreads == 0, "FFT workgroup elements");
+    constexpr int EPT = fft_elems(NT) / NT;
+    static_assert(fft_elems(NT) % NT == 0, "FFT workgroup elements");
     const int ne = nl * n;
     cplx<T> v[EPT];
     if (pass < 2) {
         const cplx<T> *sb = src + line0 * nin;
-        const double *px = precor + P.precor[0] + half_in;
+        const T *px = precor + P.precor[0] + half_in;
         const float rn = 1.0f / static_cast<float>(n);
-        double fx[EPT];        // x pre-correction (pass x), applied after all loads are issued
+        T fx[EPT];             // x pre-correction (pass x), applied after all loads are issued
         int jl[EPT];
 #pragma unroll
         for (int c = 0; c < EPT; ++c) {
-            const int e = threadIdx.x + c * kFftThreads;
+            const int e = threadIdx.x + c * NT;
             v[c] = mk<T>(T(0), T(0));
-            fx[c] = 1.0;
+            fx[c] = T(1);
             jl[c] = 0;
             if (e < ne) {
                 const int j = small_div(e, rn), f = e - __mul24(j, n);
@@ -460,8 +460,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restr
         }
 #pragma unroll
         for (int c = 0; c < EPT; ++c) {
-            const int e = threadIdx.x + c * kFftThreads;
-            if (e < ne) lds[e] = pass == 0 ? cscale<T>(v[c], T(fx[c]) * lfac[jl[c]]) : v[c];
+            const int e = threadIdx.x + c * NT;
+            if (e < ne) lds[e] = pass == 0 ? cscale<T>(v[c], fx[c] * lfac[jl[c]]) : v[c];
         }
     } else {
         const cplx<T> *sb = src + line0;
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restr
         int slot[EPT];
 #pragma unroll
         for (int c = 0; c < EPT; ++c) {
-            const int e = threadIdx.x + c * kFftThreads;
+            const int e = threadIdx.x + c * NT;
             v[c] = mk<T>(T(0), T(0));
             slot[c] = -1;
             if (e < ne) {
@@ -487,16 +487,16 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(const PairDev *__restr
     int pc = 1;
     for (int st = 0; st < P.nrad[pass]; ++st) {
         const int R = P.radix[pass][st];
-        if (R == 4) fft_stage<T, 4>(lds, nl, n, pc, ltw, s);
-        else if (R == 2) fft_stage<T, 2>(lds, nl, n, pc, ltw, s);
-        else if (R == 3) fft_stage<T, 3>(lds, nl, n, pc, ltw, s);
-        else fft_stage<T, 5>(lds, nl, n, pc, ltw, s);
+        if (R == 4) fft_stage<T, 4, NT>(lds, nl, n, pc, ltw, s);
+        else if (R == 2) fft_stage<T, 2, NT>(lds, nl, n, pc, ltw, s);
+        else if (R == 3) fft_stage<T, 3, NT>(lds, nl, n, pc, ltw, s);
+        else fft_stage<T, 5, NT>(lds, nl, n, pc, ltw, s);
         pc *= R;
     }
     // kept window: wstart is 0 (whole line) or -R with 2R < n, so wstart + q lies in (-n, n)
     cplx<T> *out = dst + line0 * wcnt;
     const float rw = 1.0f / static_cast<float>(wcnt);
-    for (int e = threadIdx.x; e < nl * wcnt; e += kFftThreads) {
+    for (int e = threadIdx.x; e < nl * wcnt; e += NT) {
         const int j = small_div(e, rw), q = e - __mul24(j, wcnt);
         int m = wst + q;
         if (m < 0) m += n;
@@ -869,14 +869,21 @@ hipError_t launch_spread(const PairDev *pairs, const int32_t *tile_pair, int64_t
 
 template <typename T>
 hipError_t launch_fft(const PairDev *pairs, const int64_t *prefix, int npairs, int64_t tiles, int pass, void *ws,
-                      const void *tw, const double *precor, int lds_elems, int max_len, double sign, hipStream_t st)
+                      const void *tw, const void *precor, int lds_elems, int max_len, double sign, hipStream_t st)
 {
     if (tiles <= 0) return hipSuccess;
     // dynamic LDS: the lines of one workgroup, then half a twiddle table of the longest line
     size_t lds = static_cast<size_t>(lds_elems + max_len / 2) * sizeof(cplx<T>);
-    hipLaunchKernelGGL(k_fft_pass<T>, dim3(static_cast<unsigned>(tiles)), dim3(kFftThreads), lds, st, pairs, prefix,
-                       npairs, pass, static_cast<cplx<T> *>(ws), static_cast<const cplx<T> *>(tw), precor, lds_elems,
-                       T(sign));
+    const T *pc = static_cast<const T *>(precor);
+    // workgroup size from the longest line of the batch (lines up to kFftSmallLen: 256 threads)
+    if (fft_threads(max_len) == kFftThreadsSmall)
+        hipLaunchKernelGGL((k_fft_pass<T, kFftThreadsSmall>), dim3(static_cast<unsigned>(tiles)), dim3(kFftThreadsSmall),
+                           lds, st, pairs, prefix, npairs, pass, static_cast<cplx<T> *>(ws),
+                           static_cast<const cplx<T> *>(tw), pc, lds_elems, T(sign));
+    else
+        hipLaunchKernelGGL((k_fft_pass<T, kFftThreads>), dim3(static_cast<unsigned>(tiles)), dim3(kFftThreads), lds, st,
+                           pairs, prefix, npairs, pass, static_cast<cplx<T> *>(ws), static_cast<const cplx<T> *>(tw),
+                           pc, lds_elems, T(sign));
     return hipGetLastError();
 }
 
@@ -963,9 +970,9 @@ template hipError_t launch_spread<double>(const PairDev *, const int32_t *, int6
                                           const int64_t *, const int64_t *, const int32_t *, const double *, int64_t,
                                           const void *, void *, int, double, hipStream_t);
 template hipError_t launch_fft<float>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,
-                                      const double *, int, int, double, hipStream_t);
+                                      const void *, int, int, double, hipStream_t);
 template hipError_t launch_fft<double>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,
-                                       const double *, int, int, double, hipStream_t);
+                                       const void *, int, int, double, hipStream_t);
 template hipError_t launch_transpose<float>(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
 template hipError_t launch_transpose<double>(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
 template hipError_t launch_interp<float>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,

@@ -499,24 +499,13 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
     for (auto &v : dp->alg_flops) v = 0.0;
 
     // Direct sub-problems are evaluated as work items of <= kDirectTile targets x
-    // <= kDirectSeg sources.  Per target chunk, its direct source chunks are merged
-    // into contiguous source ranges (chunks are contiguous in chunk order), and
+    // <= seg sources.  Per target chunk, its direct source chunks are merged into
+    // contiguous source ranges (chunks are contiguous in chunk order), and
     // consecutive target chunks with the same ranges share one target range, so
     // items are cut from the merged rectangles rather than from every small pair.
-    std::vector<std::pair<int64_t, int64_t>> ranges, group_ranges;
-    int64_t group_t0 = 0, group_t1 = 0;
-    auto emit_group = [&]() {
-        for (int64_t t0 = group_t0; t0 < group_t1; t0 += kDirectTile)
-            for (const auto &r : group_ranges)
-                for (int64_t s0 = r.first; s0 < r.second; s0 += kDirectSeg) {
-                    DirectItem it;
-                    it.tgt_off = t0;
-                    it.src_off = s0;
-                    it.tgt_cnt = static_cast<int32_t>(std::min<int64_t>(kDirectTile, group_t1 - t0));
-                    it.src_cnt = static_cast<int32_t>(std::min<int64_t>(kDirectSeg, r.second - s0));
-                    dp->direct.push_back(it);
-                }
-    };
+    struct Group { int64_t t0, t1; std::vector<std::pair<int64_t, int64_t>> ranges; };
+    std::vector<Group> groups;
+    std::vector<std::pair<int64_t, int64_t>> ranges;
     for (int32_t j = 0; j < tgt.nc; ++j) {
         double S[3];
         for (int d = 0; d < 3; ++d) S[d] = std::max(tgt.half[3 * j + d], in.s_floor[d]);
@@ -543,17 +532,38 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
                 nufft.push_back({i, j, g});
             }
         }
-        if (nt == 0) continue;
-        if (ranges == group_ranges && group_t1 == tgt.off[j]) {
-            group_t1 = tgt.off[j + 1];
-        } else {
-            emit_group();
-            group_ranges = ranges;
-            group_t0 = tgt.off[j];
-            group_t1 = tgt.off[j + 1];
-        }
+        if (nt == 0 || ranges.empty()) continue;
+        if (!groups.empty() && groups.back().ranges == ranges && groups.back().t1 == tgt.off[j])
+            groups.back().t1 = tgt.off[j + 1];
+        else
+            groups.push_back({tgt.off[j], tgt.off[j + 1], ranges});
     }
-    emit_group();
+    // Segment length: the longest of kDirectSeg, kDirectSeg/2, ... (>= 2 LDS
+    // tiles) that still gives enough items to fill the GPU.  Items are listed
+    // source-segment-major: consecutive workgroups (spread over the XCDs) work on
+    // the same source segment for different target tiles, so a segment is
+    // fetched into each XCD's L2 once rather than once per tile.
+    int64_t seg = kDirectSeg;
+    for (; seg > 2 * kDirectSrcTile; seg /= 2) {
+        int64_t items = 0;
+        for (const Group &g : groups) {
+            int64_t segs = 0;
+            for (const auto &r : g.ranges) segs += (r.second - r.first + seg - 1) / seg;
+            items += segs * ((g.t1 - g.t0 + kDirectTile - 1) / kDirectTile);
+        }
+        if (items >= kDirectMinItems) break;
+    }
+    for (const Group &g : groups)
+        for (const auto &r : g.ranges)
+            for (int64_t s0 = r.first; s0 < r.second; s0 += seg)
+                for (int64_t t0 = g.t0; t0 < g.t1; t0 += kDirectTile) {
+                    DirectItem it;
+                    it.tgt_off = t0;
+                    it.src_off = s0;
+                    it.tgt_cnt = static_cast<int32_t>(std::min<int64_t>(kDirectTile, g.t1 - t0));
+                    it.src_cnt = static_cast<int32_t>(std::min<int64_t>(seg, r.second - s0));
+                    dp->direct.push_back(it);
+                }
     dp->alg_flops[HVOX_K_DIRECT] = dp->direct_terms;
 
     // group NUFFT sub-problems into batches sharing the workspace
@@ -612,7 +622,7 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
                 pd.wstart[d] = g.wstart[d];
                 pd.wcount[d] = g.wcount[d];
                 pd.nrad[d] = factor_radices(g.n2[d], pd.radix[d]);
-                pd.lines_per_tile[d] = std::max(1, std::min(kFftMaxLines, kFftElems / g.n2[d]));
+                pd.lines_per_tile[d] = fft_lines(g.n2[d]);
                 auto key = std::make_pair(g.n1[d], g.n2[d]);
                 auto it = precor_map->find(key);
                 if (it == precor_map->end()) {
