@@ -95,7 +95,7 @@ def kernel_table(plan, bufs):
 HBM_KERNELS = ("zero", "spread", "fft_x", "fft_y", "fft_z", "interp", "finalize", "transpose", "prephase")
 
 
-def roofline_entry(st, dtype, name=None):
+def roofline_entry(st, dtype, name=None, rows=1):
     """Roofline of one kernel (default: the one taking the most time): its
     algorithmic bytes (or VALU lane-operations) per launch over its average
     launch duration, against the MI355X peak."""
@@ -112,20 +112,23 @@ def roofline_entry(st, dtype, name=None):
         return name, {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
     # direct summation: VALU-bound; one term costs VALU_OPS_PER_TERM lane-operations
-    ops = VALU_OPS_PER_TERM[dtype]
+    ops = VALU_OPS_PER_TERM[(dtype, rows)]
     achieved = v["alg_flops"] / n * ops / avg_s / 1e12 if avg_s > 0 else 0.0
     return name, {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
                   "frac": achieved / VALU_PEAK_TOPS, "traffic": None}
 
 
-# VALU instructions issued per (target, source) term by the direct kernel's
-# inner loop, counted from its gfx950 assembly (LDS reads and scalar loop
-# control excluded): float32 plan 89 per unrolled iteration of 4 sources x 2
-# targets (float64 dot and fractional part, conversion, hardware sine and
-# cosine, complex multiply-accumulate); float64 plan 86 per 2-term iteration
-# (float64 dot, quarter-turn reduction, Maclaurin sine and cosine, rotation,
-# complex multiply-accumulate).  Each is one lane-operation per lane.
-VALU_OPS_PER_TERM = {"f32": 89.0 / 8.0, "f64": 86.0 / 2.0}
+# VALU instructions issued per (target, source, data row) by the direct
+# kernel's inner loop, counted from its gfx950 assembly (LDS reads and scalar
+# loop control excluded), by plan precision and rows per launch.  Float32: per
+# unrolled iteration of 4 sources x 2 targets (1 row) or 2 x 2 (2-4 rows), the
+# float64 dot product and fractional part, the conversion, hardware sine and
+# cosine (shared by the rows) and one complex multiply-accumulate per row;
+# float64: per iteration of 3 sources x 2 targets, the float64 dot product,
+# quarter-turn reduction, Maclaurin sine and cosine and rotation (shared) and
+# the per-row multiply-accumulate.  Each is one lane-operation per lane.
+VALU_OPS_PER_TERM = {("f32", 1): 89 / 8, ("f32", 2): 62 / 8, ("f32", 3): 78 / 12, ("f32", 4): 94 / 16,
+                     ("f64", 1): 203 / 6, ("f64", 2): 222 / 12, ("f64", 3): 245 / 18, ("f64", 4): 264 / 24}
 
 
 def cpu_baseline(wl, target_s=12.0):
@@ -300,7 +303,7 @@ def main():
             roofs = {}
             for k, v in r["stats"].items():
                 if v["launches"] and v["ms"] > 0 and (v["alg_bytes"] or k == "direct"):
-                    _, rf = roofline_entry(r["stats"], "f32", k)
+                    _, rf = roofline_entry(r["stats"], "f32", k, rows=rows)
                     roofs[k] = {"bound": rf["bound"], "achieved": round(rf["achieved"], 1), "unit": rf["unit"],
                                 "frac": round(rf["frac"], 4)}
             ent["rooflines"] = roofs
