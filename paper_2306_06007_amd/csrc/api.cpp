@@ -362,6 +362,7 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
     for (int64_t i = 0; i < nt; ++i) off[i + 1] = off[i] + counts[i];
     // batches whose grid 1 is mostly empty: clear it with one fill, spread only the non-empty tiles
     dp.tile_list.clear();
+    const double delta = pl->hp.prm.dtype == HVOX_F64 ? 16.0 : 8.0;
     for (Batch &b : dp.batches) {
         const int64_t t0 = dp.pairs[b.pair0].tile0;
         int64_t nonempty = 0;
@@ -370,9 +371,24 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
         b.list_off = static_cast<int64_t>(dp.tile_list.size());
         b.list_cnt = 0;
         if (!b.sparse) continue;
-        for (int64_t t = 0; t < b.stiles; ++t)
-            if (counts[t0 + t] > 0) dp.tile_list.push_back(t);
+        // the fill writes the batch's grid-1 region, spreading only the listed tiles' cells
+        double listed_cells = 0.0;
+        for (int64_t i = 0; i < b.npairs; ++i) {
+            const PairDev &pd = dp.pairs[b.pair0 + i];
+            const int64_t nt = static_cast<int64_t>(pd.ntile[0]) * pd.ntile[1] * pd.ntile[2];
+            for (int64_t lt = 0; lt < nt; ++lt) {
+                if (counts[pd.tile0 + lt] == 0) continue;
+                dp.tile_list.push_back(pd.tile0 + lt - t0);
+                const int64_t tx = lt % pd.ntile[0], ty = (lt / pd.ntile[0]) % pd.ntile[1];
+                const int64_t tz = lt / (static_cast<int64_t>(pd.ntile[0]) * pd.ntile[1]);
+                listed_cells += static_cast<double>(std::min<int64_t>(kTileX, pd.n1[0] - tx * kTileX)) *
+                                std::min<int64_t>(kTileY, pd.n1[1] - ty * kTileY) *
+                                std::min<int64_t>(kTileZ, pd.n1[2] - tz * kTileZ);
+            }
+        }
         b.list_cnt = static_cast<int64_t>(dp.tile_list.size()) - b.list_off;
+        dp.alg_bytes[HVOX_K_SPREAD] -= delta * (static_cast<double>(b.g_cnt) - listed_cells);
+        dp.alg_bytes[HVOX_K_ZERO] += delta * static_cast<double>(b.g_cnt);
     }
     if (!dp.tile_list.empty()) {
         hipError_t el = upload(pl, dp.tile_list, &dd->tile_list, st);

@@ -692,6 +692,7 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
         k = k1;
     }
     dp->alg_bytes[HVOX_K_FINAL] = tgt.n * (16.0 + 4.0 + delta);
+    dp->alg_bytes[HVOX_K_ZERO] = 16.0 * tgt.n;   // accumulator clear (grid-1 fills of sparse batches added at binning)
 }
 
 }  // namespace
