@@ -192,16 +192,15 @@ __global__ void k_prephase(const PairDev *__restrict__ pairs, const int64_t *__r
     stage[g] = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
 }
 
-// One workgroup per grid-1 tile of kTileZ x kTileY x kTileX cells, held in
-// LDS.  The tile's sources (from the plan-time binning) are staged
-// kSpreadBatch at a time: footprint origin, footprint clipped to the tile, the
-// 3w kernel values and the pre-phased value.  The work is then split into
-// units of one (source, y, z) row of a clipped footprint; a unit adds its run
-// of x cells into the LDS tile with LDS float atomics, so every lane does
-// useful work whatever the footprint covers.  The tile is written to grid 1
-// once, row by row (no global atomics, no separate clearing of grid 1).  The
-// tile's sub-problem comes from a plan-time table and the values from the
-// pre-phase pass.
+// One workgroup per grid-1 tile of kTileX x kTileY x kTileZ cells.  Each
+// wavefront owns an 8 x 8 (x, y) patch of the tile face, each lane one column
+// of kTileZ cells in registers.  The tile's sources (plan-time binning) are
+// staged kSpreadBatch at a time (pre-phased value, footprint origin, 3w kernel
+// values in LDS); a wavefront skips every source whose footprint misses its
+// patch, so most lanes of the wavefronts that do work are covered.  The tile
+// then goes through LDS to be written to grid 1 once, in full rows (no
+// atomics: for a given plan the result is deterministic).  The tile's
+// sub-problem comes from a plan-time table, the values from the pre-phase pass.
 template <typename T>
 __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pairs, const int32_t *__restrict__ tile_pair,
                                                 int64_t tile_base, const int64_t *__restrict__ pprefix,
@@ -211,16 +210,16 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
                                                 int64_t nsrc, const cplx<T> *__restrict__ stage,
                                                 cplx<T> *__restrict__ ws, int w, T beta)
 {
-    constexpr int kCells = kTileX * kTileY * kTileZ;
-    __shared__ T tre[kCells], tim[kCells];                 // the tile, z-major, x fastest
+    static_assert(kTileX == 32 && kTileY == 8, "four 8 x 8 patches per tile face");
     __shared__ T ker[kSpreadBatch][3 * kWMax];
     __shared__ T frac[kSpreadBatch][3];
     __shared__ cplx<T> val[kSpreadBatch];
-    __shared__ int org[kSpreadBatch][3];                   // footprint origin, tile coordinates
-    __shared__ int clip[kSpreadBatch][4];                  // x0, x extent, y0, z0 of the clipped footprint
-    __shared__ int uext[kSpreadBatch][2];                  // y and z extents
-    __shared__ int upre[kSpreadBatch + 1];                 // prefix of (y, z) units per staged source
+    __shared__ int org[kSpreadBatch][3];
+    __shared__ cplx<T> tileb[kTileZ][kTileY][kTileX + 1];   // write-out buffer (padded rows)
     const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int px0 = wave * 8;                              // this wavefront's patch: x in [px0, px0 + 8)
+    const int ax = px0 + (lane & 7), ay = lane >> 3;
     const int64_t gt = tile_base + (tile_list ? tile_list[blockIdx.x] : (int64_t)blockIdx.x);
     const int p = tile_pair[gt];
     const int64_t r0 = toff[gt], r1 = toff[gt + 1];
@@ -234,7 +233,9 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
     const int w3 = 3 * w;
     const float rw = 1.0f / static_cast<float>(w), rw3 = 1.0f / static_cast<float>(w3);
     const cplx<T> *sv = stage + pprefix[p] - P.src_off;   // staged value of source n: sv[n]
-    for (int c = tid; c < kCells; c += 256) tre[c] = tim[c] = T(0);
+    T accr[kTileZ], acci[kTileZ];
+#pragma unroll
+    for (int z = 0; z < kTileZ; ++z) accr[z] = acci[z] = T(0);
 
     for (int64_t base = r0; base < r1; base += kSpreadBatch) {
         const int cnt = (int)min((int64_t)kSpreadBatch, r1 - base);
@@ -244,23 +245,11 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
             double xp[3], t[3];
             int c0[3];
             source_footprint(P, xyz, nsrc, n, w, xp, t, c0);
-            const int o[3] = {c0[0] - ox, c0[1] - oy, c0[2] - oz};
-            const int tdim[3] = {kTileX, kTileY, kTileZ};
-            int lo[3], ext[3];
-            for (int d = 0; d < 3; ++d) {
-                org[tid][d] = o[d];
-                lo[d] = max(o[d], 0);
-                ext[d] = max(0, min(o[d] + w, tdim[d]) - lo[d]);
-            }
-            clip[tid][0] = lo[0];
-            clip[tid][1] = ext[0];
-            clip[tid][2] = lo[1];
-            clip[tid][3] = lo[2];
-            uext[tid][0] = ext[0] > 0 ? ext[1] : 0;
-            uext[tid][1] = ext[2];
-            val[tid] = sv[n];
-            // first footprint cell minus the source position, in grid-1 units
             for (int d = 0; d < 3; ++d) frac[tid][d] = T((double)(c0[d] - P.n1[d] / 2) - t[d]);
+            org[tid][0] = c0[0] - ox;
+            org[tid][1] = c0[1] - oy;
+            org[tid][2] = c0[2] - oz;
+            val[tid] = sv[n];
         }
         __syncthreads();
         for (int i = tid; i < cnt * w3; i += 256) {
@@ -268,37 +257,28 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
             const int d = small_div(r, rw), q = r - __mul24(d, w);
             ker[j][r] = es_kernel((frac[j][d] + T(q)) * two_over_w, beta);
         }
-        static_assert(kSpreadBatch <= 64, "one wavefront scans the staged sources");
-        if (tid < 64) {   // prefix of units over the staged sources (one wavefront)
-            int u = tid < cnt ? uext[tid][0] * uext[tid][1] : 0;
-            for (int off = 1; off < 64; off <<= 1) {
-                const int v = __shfl_up(u, off, 64);
-                if (tid >= off) u += v;
-            }
-            upre[tid + 1] = u;
-            if (tid == 0) upre[0] = 0;
-        }
         __syncthreads();
-        const int total = upre[cnt];
-        for (int u = tid; u < total; u += 256) {
-            int j = 0;   // staged source of unit u: last j with upre[j] <= u
-            for (int step = kSpreadBatch / 2; step > 0; step >>= 1)
-                if (j + step <= cnt - 1 && upre[j + step] <= u) j += step;
-            const int r = u - upre[j];
-            const int ez = uext[j][1];
-            const int iy = small_div(r, 1.0f / static_cast<float>(ez)), iz = r - __mul24(iy, ez);
-            const int y = clip[j][2] + iy, z = clip[j][3] + iz;
-            const T kyz = ker[j][w + (y - org[j][1])] * ker[j][2 * w + (z - org[j][2])];
-            const T vr = val[j].x * kyz, vi = val[j].y * kyz;
-            const int x0 = clip[j][0], ex = clip[j][1], kx0 = x0 - org[j][0];
-            const int row = (z * kTileY + y) * kTileX;
-            for (int i = 0; i < ex; ++i) {
-                const T kx = ker[j][kx0 + i];
-                atomicAdd(&tre[row + x0 + i], vr * kx);
-                atomicAdd(&tim[row + x0 + i], vi * kx);
+        for (int j = 0; j < cnt; ++j) {
+            const int oxj = org[j][0];
+            if (oxj + w <= px0 || oxj >= px0 + 8) continue;     // footprint misses this wavefront's patch
+            const int qx = ax - oxj, qy = ay - org[j][1];
+            if ((unsigned)qx >= (unsigned)w || (unsigned)qy >= (unsigned)w) continue;
+            const T kxy = ker[j][qx] * ker[j][w + qy];
+            const T vr = val[j].x * kxy, vi = val[j].y * kxy;
+            const int oz0 = org[j][2];
+#pragma unroll
+            for (int z = 0; z < kTileZ; ++z) {
+                const int qz = z - oz0;
+                if ((unsigned)qz < (unsigned)w) {
+                    const T kz = ker[j][2 * w + qz];
+                    accr[z] += vr * kz;
+                    acci[z] += vi * kz;
+                }
             }
         }
     }
+#pragma unroll
+    for (int z = 0; z < kTileZ; ++z) tileb[z][ay][ax] = mk<T>(accr[z], acci[z]);
     __syncthreads();
     const int x = tid % kTileX, y = tid / kTileX;
     const int gx = ox + x, gy = oy + y;
@@ -307,8 +287,7 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
 #pragma unroll
         for (int z = 0; z < kTileZ; ++z) {
             const int gz = oz + z;
-            const int c = (z * kTileY + y) * kTileX + x;
-            if (gz < P.n1[2]) grid[((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx] = mk<T>(tre[c], tim[c]);
+            if (gz < P.n1[2]) grid[((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx] = tileb[z][y][x];
         }
     }
 }
@@ -339,6 +318,23 @@ __device__ __forceinline__ void dft_small(cplx<T> *u, T s)
         u[2] = csub<T>(a, c);
         u[1] = cadd<T>(b, id);
         u[3] = csub<T>(b, id);
+    } else if constexpr (R == 8) {
+        // two 4-point DFTs (even and odd inputs) joined with w^m, w = exp(s 2 pi i / 8)
+        const T h = T(0.70710678118654752440);
+        cplx<T> e[4] = {u[0], u[2], u[4], u[6]}, o[4] = {u[1], u[3], u[5], u[7]};
+        dft_small<T, 4>(e, s);
+        dft_small<T, 4>(o, s);
+        const cplx<T> o1 = mk<T>(h * (o[1].x - s * o[1].y), h * (o[1].y + s * o[1].x));    // w^1 = (1 + i s)/sqrt2
+        const cplx<T> o2 = cmuli<T>(o[2], s);                                              // w^2 = i s
+        const cplx<T> o3 = mk<T>(-h * (o[3].x + s * o[3].y), h * (s * o[3].x - o[3].y));   // w^3 = (-1 + i s)/sqrt2
+        u[0] = cadd<T>(e[0], o[0]);
+        u[4] = csub<T>(e[0], o[0]);
+        u[1] = cadd<T>(e[1], o1);
+        u[5] = csub<T>(e[1], o1);
+        u[2] = cadd<T>(e[2], o2);
+        u[6] = csub<T>(e[2], o2);
+        u[3] = cadd<T>(e[3], o3);
+        u[7] = csub<T>(e[3], o3);
     } else {   // R == 5
         const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
         const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);
@@ -382,18 +378,11 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int p, const cplx<T> *tw,
             const int lb = __mul24(j, n);
             obase[c] = lb + __mul24(g, pR) + k;
             const int tk = __mul24(k, twstep);
-            const int half = n >> 1;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 cplx<T> u = lds[lb + i + q * nbf];
-                if (q > 0) {
-                    // exponent q k twstep < n; the LDS table holds exp(s 2 pi i j/n) for j < n/2
-                    const int jt = q * tk;
-                    const bool hi = jt >= half;
-                    cplx<T> t = tw[hi ? jt - half : jt];
-                    if (hi) { t.x = -t.x; t.y = -t.y; }
-                    u = cmul<T>(u, t);
-                }
+                // exponent q k twstep < n; the LDS table holds exp(s 2 pi i j/n), j < n
+                if (q > 0) u = cmul<T>(u, tw[q * tk]);
                 v[c][q] = u;
             }
             dft_small<T, R>(v[c], s);
@@ -427,7 +416,7 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
 {
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *lds = reinterpret_cast<cplx<T> *>(smem_raw);
-    cplx<T> *ltw = lds + tw_off;              // exp(s 2 pi i j/n), j < n/2, after the lines
+    cplx<T> *ltw = lds + tw_off;              // exp(s 2 pi i j/n), j < n, after the lines
     __shared__ T lfac[kFftMaxLines];
     const int p = (int)find_segment(prefix, npairs, blockIdx.x);
     const PairDev &P = pairs[p];
@@ -448,7 +437,7 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
     {
         // twiddles of this line length, staged with the data (sign s applied here)
         const cplx<T> *tw = twtab + P.tw[pass];
-        for (int j = threadIdx.x; j < half_n; j += NT) {
+        for (int j = threadIdx.x; j < n; j += NT) {
             cplx<T> t = tw[j];
             t.y *= -s;   // table holds exp(-2 pi i j/n); s = -1 keeps it, +1 conjugates
             ltw[j] = t;
@@ -520,7 +509,8 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
     int pc = 1;
     for (int st = 0; st < P.nrad[pass]; ++st) {
         const int R = P.radix[pass][st];
-        if (R == 4) fft_stage<T, 4, NT>(lds, nl, n, pc, ltw, s);
+        if (R == 8) fft_stage<T, 8, NT>(lds, nl, n, pc, ltw, s);
+        else if (R == 4) fft_stage<T, 4, NT>(lds, nl, n, pc, ltw, s);
         else if (R == 2) fft_stage<T, 2, NT>(lds, nl, n, pc, ltw, s);
         else if (R == 3) fft_stage<T, 3, NT>(lds, nl, n, pc, ltw, s);
         else fft_stage<T, 5, NT>(lds, nl, n, pc, ltw, s);
@@ -905,8 +895,8 @@ hipError_t launch_fft(const PairDev *pairs, const int64_t *prefix, int npairs, i
                       const void *tw, const void *precor, int lds_elems, int max_len, double sign, hipStream_t st)
 {
     if (tiles <= 0) return hipSuccess;
-    // dynamic LDS: the lines of one workgroup, then half a twiddle table of the longest line
-    size_t lds = static_cast<size_t>(lds_elems + max_len / 2) * sizeof(cplx<T>);
+    // dynamic LDS: the lines of one workgroup, then the twiddle table of the longest line
+    size_t lds = static_cast<size_t>(lds_elems + max_len) * sizeof(cplx<T>);
     const T *pc = static_cast<const T *>(precor);
     // workgroup size from the longest line of the batch (lines up to kFftSmallLen: 256 threads)
     if (fft_threads(max_len) == kFftThreadsSmall)

@@ -102,11 +102,12 @@ int32_t smooth_even(int64_t n)
     }
 }
 
-// Radix stages of an n-point FFT: 4s, then a 2, then 3s, then 5s.
+// Radix stages of an n-point FFT: 8s, then a 4 or a 2, then 3s, then 5s.
 int factor_radices(int32_t n, uint8_t *radix)
 {
     int ns = 0;
     int32_t m = n;
+    while (m % 8 == 0) { if (ns >= kMaxStages) return -1; radix[ns++] = 8; m /= 8; }
     while (m % 4 == 0) { if (ns >= kMaxStages) return -1; radix[ns++] = 4; m /= 4; }
     while (m % 2 == 0) { if (ns >= kMaxStages) return -1; radix[ns++] = 2; m /= 2; }
     while (m % 3 == 0) { if (ns >= kMaxStages) return -1; radix[ns++] = 3; m /= 3; }
