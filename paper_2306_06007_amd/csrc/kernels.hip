@@ -192,15 +192,13 @@ __global__ void k_prephase(const PairDev *__restrict__ pairs, const int64_t *__r
     stage[g] = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
 }
 
-// One workgroup per grid-1 tile of kTileX x kTileY x kTileZ cells.  Each
-// wavefront owns an 8 x 8 (x, y) patch of the tile face, each lane one column
-// of kTileZ cells in registers.  The tile's sources (plan-time binning) are
-// staged kSpreadBatch at a time (pre-phased value, footprint origin, 3w kernel
-// values in LDS); a wavefront skips every source whose footprint misses its
-// patch, so most lanes of the wavefronts that do work are covered.  The tile
-// then goes through LDS to be written to grid 1 once, in full rows (no
-// atomics: for a given plan the result is deterministic).  The tile's
-// sub-problem comes from a plan-time table, the values from the pre-phase pass.
+// One workgroup per grid-1 tile.  Thread (x, y) of the 32 x 8 face owns the
+// kTileZ (16) cells of its column; the tile's sources are staged kSpreadBatch at a
+// time (their pre-phased values, footprint origin and 3w kernel values in
+// LDS), every thread adds the contributions that fall in its cells, and the
+// whole tile is written once (no atomics; for a given plan the result is
+// deterministic).  The tile's sub-problem comes from a plan-time table, its
+// source list from the plan-time binning, the values from the pre-phase pass.
 template <typename T>
 __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pairs, const int32_t *__restrict__ tile_pair,
                                                 int64_t tile_base, const int64_t *__restrict__ pprefix,
@@ -210,16 +208,11 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
                                                 int64_t nsrc, const cplx<T> *__restrict__ stage,
                                                 cplx<T> *__restrict__ ws, int w, T beta)
 {
-    static_assert(kTileX == 32 && kTileY == 8, "four 8 x 8 patches per tile face");
     __shared__ T ker[kSpreadBatch][3 * kWMax];
     __shared__ T frac[kSpreadBatch][3];
     __shared__ cplx<T> val[kSpreadBatch];
     __shared__ int org[kSpreadBatch][3];
-    __shared__ cplx<T> tileb[kTileZ][kTileY][kTileX + 1];   // write-out buffer (padded rows)
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int px0 = wave * 8;                              // this wavefront's patch: x in [px0, px0 + 8)
-    const int ax = px0 + (lane & 7), ay = lane >> 3;
     const int64_t gt = tile_base + (tile_list ? tile_list[blockIdx.x] : (int64_t)blockIdx.x);
     const int p = tile_pair[gt];
     const int64_t r0 = toff[gt], r1 = toff[gt + 1];
@@ -229,6 +222,7 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
     const int ty = (int)((lt / P.ntile[0]) % P.ntile[1]);
     const int tz = (int)(lt / ((int64_t)P.ntile[0] * P.ntile[1]));
     const int ox = tx * kTileX, oy = ty * kTileY, oz = tz * kTileZ;
+    const int x = tid % kTileX, y = tid / kTileX;
     const T two_over_w = T(2) / T(w);
     const int w3 = 3 * w;
     const float rw = 1.0f / static_cast<float>(w), rw3 = 1.0f / static_cast<float>(w3);
@@ -259,9 +253,7 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
         }
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
-            const int oxj = org[j][0];
-            if (oxj + w <= px0 || oxj >= px0 + 8) continue;     // footprint misses this wavefront's patch
-            const int qx = ax - oxj, qy = ay - org[j][1];
+            const int qx = x - org[j][0], qy = y - org[j][1];
             if ((unsigned)qx >= (unsigned)w || (unsigned)qy >= (unsigned)w) continue;
             const T kxy = ker[j][qx] * ker[j][w + qy];
             const T vr = val[j].x * kxy, vi = val[j].y * kxy;
@@ -277,17 +269,13 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
             }
         }
     }
-#pragma unroll
-    for (int z = 0; z < kTileZ; ++z) tileb[z][ay][ax] = mk<T>(accr[z], acci[z]);
-    __syncthreads();
-    const int x = tid % kTileX, y = tid / kTileX;
     const int gx = ox + x, gy = oy + y;
     if (gx < P.n1[0] && gy < P.n1[1]) {
         cplx<T> *grid = ws + P.bufG;
 #pragma unroll
         for (int z = 0; z < kTileZ; ++z) {
             const int gz = oz + z;
-            if (gz < P.n1[2]) grid[((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx] = tileb[z][y][x];
+            if (gz < P.n1[2]) grid[((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx] = mk<T>(accr[z], acci[z]);
         }
     }
 }
