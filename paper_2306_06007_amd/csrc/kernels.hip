@@ -192,17 +192,13 @@ __global__ void k_prephase(const PairDev *__restrict__ pairs, const int64_t *__r
     stage[g] = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
 }
 
-// One workgroup per grid-1 tile of kTileZ x kTileY x kTileX cells, held in
-// LDS (rows and planes padded by one cell so that they map to different LDS
-// banks).  The tile's sources (from the plan-time binning) are staged
-// kSpreadBatch at a time: footprint origin, footprint clipped to the tile, the
-// 3w kernel values and the pre-phased value.  The work is then split into
-// units of one (source, y, z) row of a clipped footprint; a unit adds its run
-// of x cells into the LDS tile with LDS float atomics, so every lane does
-// useful work whatever the footprint covers.  The tile is written to grid 1
-// once, row by row (no global atomics, no separate clearing of grid 1).  The
-// tile's sub-problem comes from a plan-time table and the values from the
-// pre-phase pass.
+// One workgroup per grid-1 tile.  Thread (x, y) of the 32 x 8 face owns the
+// kTileZ cells of its column; the tile's sources are staged kSpreadBatch at a
+// time (their pre-phased values, footprint origin and 3w kernel values in
+// LDS), every thread adds the contributions that fall in its cells, and the
+// whole tile is written once (no atomics; for a given plan the result is
+// deterministic).  The tile's sub-problem comes from a plan-time table, its
+// source list from the plan-time binning, the values from the pre-phase pass.
 template <typename T>
 __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pairs, const int32_t *__restrict__ tile_pair,
                                                 int64_t tile_base, const int64_t *__restrict__ pprefix,
@@ -212,17 +208,10 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
                                                 int64_t nsrc, const cplx<T> *__restrict__ stage,
                                                 cplx<T> *__restrict__ ws, int w, T beta)
 {
-    constexpr int kRow = kTileX + 1;                       // padded rows and planes: neighbouring rows and
-    constexpr int kPlane = kRow * kTileY + 1;              // z-planes start on different LDS banks
-    constexpr int kCells = kPlane * kTileZ;
-    __shared__ T tre[kCells], tim[kCells];                 // the tile, z-major, x fastest
     __shared__ T ker[kSpreadBatch][3 * kWMax];
     __shared__ T frac[kSpreadBatch][3];
     __shared__ cplx<T> val[kSpreadBatch];
-    __shared__ int org[kSpreadBatch][3];                   // footprint origin, tile coordinates
-    __shared__ int clip[kSpreadBatch][4];                  // x0, x extent, y0, z0 of the clipped footprint
-    __shared__ int uext[kSpreadBatch][2];                  // y and z extents
-    __shared__ int upre[kSpreadBatch + 1];                 // prefix of (y, z) units per staged source
+    __shared__ int org[kSpreadBatch][3];
     const int tid = threadIdx.x;
     const int64_t gt = tile_base + (tile_list ? tile_list[blockIdx.x] : (int64_t)blockIdx.x);
     const int p = tile_pair[gt];
@@ -233,11 +222,14 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
     const int ty = (int)((lt / P.ntile[0]) % P.ntile[1]);
     const int tz = (int)(lt / ((int64_t)P.ntile[0] * P.ntile[1]));
     const int ox = tx * kTileX, oy = ty * kTileY, oz = tz * kTileZ;
+    const int x = tid % kTileX, y = tid / kTileX;
     const T two_over_w = T(2) / T(w);
     const int w3 = 3 * w;
     const float rw = 1.0f / static_cast<float>(w), rw3 = 1.0f / static_cast<float>(w3);
     const cplx<T> *sv = stage + pprefix[p] - P.src_off;   // staged value of source n: sv[n]
-    for (int c = tid; c < kCells; c += 256) tre[c] = tim[c] = T(0);
+    T accr[kTileZ], acci[kTileZ];
+#pragma unroll
+    for (int z = 0; z < kTileZ; ++z) accr[z] = acci[z] = T(0);
 
     for (int64_t base = r0; base < r1; base += kSpreadBatch) {
         const int cnt = (int)min((int64_t)kSpreadBatch, r1 - base);
@@ -247,23 +239,11 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
             double xp[3], t[3];
             int c0[3];
             source_footprint(P, xyz, nsrc, n, w, xp, t, c0);
-            const int o[3] = {c0[0] - ox, c0[1] - oy, c0[2] - oz};
-            const int tdim[3] = {kTileX, kTileY, kTileZ};
-            int lo[3], ext[3];
-            for (int d = 0; d < 3; ++d) {
-                org[tid][d] = o[d];
-                lo[d] = max(o[d], 0);
-                ext[d] = max(0, min(o[d] + w, tdim[d]) - lo[d]);
-            }
-            clip[tid][0] = lo[0];
-            clip[tid][1] = ext[0];
-            clip[tid][2] = lo[1];
-            clip[tid][3] = lo[2];
-            uext[tid][0] = ext[0] > 0 ? ext[1] : 0;
-            uext[tid][1] = ext[2];
-            val[tid] = sv[n];
-            // first footprint cell minus the source position, in grid-1 units
             for (int d = 0; d < 3; ++d) frac[tid][d] = T((double)(c0[d] - P.n1[d] / 2) - t[d]);
+            org[tid][0] = c0[0] - ox;
+            org[tid][1] = c0[1] - oy;
+            org[tid][2] = c0[2] - oz;
+            val[tid] = sv[n];
         }
         __syncthreads();
         for (int i = tid; i < cnt * w3; i += 256) {
@@ -271,47 +251,31 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
             const int d = small_div(r, rw), q = r - __mul24(d, w);
             ker[j][r] = es_kernel((frac[j][d] + T(q)) * two_over_w, beta);
         }
-        static_assert(kSpreadBatch <= 64, "one wavefront scans the staged sources");
-        if (tid < 64) {   // prefix of units over the staged sources (one wavefront)
-            int u = tid < cnt ? uext[tid][0] * uext[tid][1] : 0;
-            for (int off = 1; off < 64; off <<= 1) {
-                const int v = __shfl_up(u, off, 64);
-                if (tid >= off) u += v;
-            }
-            upre[tid + 1] = u;
-            if (tid == 0) upre[0] = 0;
-        }
         __syncthreads();
-        const int total = upre[cnt];
-        for (int u = tid; u < total; u += 256) {
-            int j = 0;   // staged source of unit u: last j with upre[j] <= u
-            for (int step = kSpreadBatch / 2; step > 0; step >>= 1)
-                if (j + step <= cnt - 1 && upre[j + step] <= u) j += step;
-            const int r = u - upre[j];
-            const int ez = uext[j][1];
-            const int iy = small_div(r, 1.0f / static_cast<float>(ez)), iz = r - __mul24(iy, ez);
-            const int y = clip[j][2] + iy, z = clip[j][3] + iz;
-            const T kyz = ker[j][w + (y - org[j][1])] * ker[j][2 * w + (z - org[j][2])];
-            const T vr = val[j].x * kyz, vi = val[j].y * kyz;
-            const int x0 = clip[j][0], ex = clip[j][1], kx0 = x0 - org[j][0];
-            const int row = z * kPlane + y * kRow;
-            for (int i = 0; i < ex; ++i) {
-                const T kx = ker[j][kx0 + i];
-                atomicAdd(&tre[row + x0 + i], vr * kx);
-                atomicAdd(&tim[row + x0 + i], vi * kx);
+        for (int j = 0; j < cnt; ++j) {
+            const int qx = x - org[j][0], qy = y - org[j][1];
+            if ((unsigned)qx >= (unsigned)w || (unsigned)qy >= (unsigned)w) continue;
+            const T kxy = ker[j][qx] * ker[j][w + qy];
+            const T vr = val[j].x * kxy, vi = val[j].y * kxy;
+            const int oz0 = org[j][2];
+#pragma unroll
+            for (int z = 0; z < kTileZ; ++z) {
+                const int qz = z - oz0;
+                if ((unsigned)qz < (unsigned)w) {
+                    const T kz = ker[j][2 * w + qz];
+                    accr[z] += vr * kz;
+                    acci[z] += vi * kz;
+                }
             }
         }
     }
-    __syncthreads();
-    const int x = tid % kTileX, y = tid / kTileX;
     const int gx = ox + x, gy = oy + y;
     if (gx < P.n1[0] && gy < P.n1[1]) {
         cplx<T> *grid = ws + P.bufG;
 #pragma unroll
         for (int z = 0; z < kTileZ; ++z) {
             const int gz = oz + z;
-            const int c = z * kPlane + y * kRow + x;
-            if (gz < P.n1[2]) grid[((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx] = mk<T>(tre[c], tim[c]);
+            if (gz < P.n1[2]) grid[((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx] = mk<T>(accr[z], acci[z]);
         }
     }
 }
