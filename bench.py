@@ -158,7 +158,7 @@ def cpu_baseline(wl, target_s=12.0):
     return info, (rv, Vs), (rp, Is)
 
 
-def serving_run():
+def serving_run(slots=8, planners=8):
     """64 Poisson-arriving requests (mean gap 10 ms), each a synthesis or an
     analysis with log-uniform 1e4..1e6 visibilities and pixels on subsampled
     SKA-like / LOFAR-like baselines, float32 at eps = 1e-4, through the
@@ -167,12 +167,15 @@ def serving_run():
     from paper_2306_06007_amd import workloads as W
     reqs = W.serving_requests(seed=4)
     log(f"serving: {len(reqs)} requests generated")
-    ex = serve.GpuExecutor(eps=1e-4, dtype="f32", slots=4, planners=8, workspace_bytes=1 << 30)
+    ex = serve.GpuExecutor(eps=1e-4, dtype="f32", slots=slots, planners=planners, workspace_bytes=1 << 30)
     srv = serve.Server(ex, hbm_budget_bytes=64e9)
     res = srv.run(reqs, keep_outputs=False)
     ex.close()
     s = serve.summarize(res)
     s["max_in_flight"] = max(n for _, _, n, _ in srv.log)
+    s["slots"], s["planners"] = slots, planners
+    s["plan_seconds_mean"] = float(sum(ex.plan_seconds) / max(1, len(ex.plan_seconds)))
+    s["plan_seconds_total"] = float(sum(ex.plan_seconds))
     return s
 
 

@@ -70,6 +70,7 @@ class GpuExecutor:
         self.cache = collections.OrderedDict()      # key -> Plan
         self.in_use = collections.Counter()         # key -> requests currently using the plan
         self.lock = threading.Lock()
+        self.plan_seconds = []                      # host + device time of every plan built
 
     @property
     def slots(self):
@@ -93,8 +94,11 @@ class GpuExecutor:
                 self.cache.move_to_end(key)
                 self.in_use[key] += 1
                 return key, plan
+        t0 = time.perf_counter()
         plan = Plan(req.uvw, req.xyz, self.eps, self.dtype, stream=stream, workspace_bytes=self.workspace_bytes,
                     **self.plan_opts)
+        with self.lock:
+            self.plan_seconds.append(time.perf_counter() - t0)
         with self.lock:
             if key in self.cache:               # planned concurrently by another worker
                 plan.free()
