@@ -48,10 +48,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, dtype: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary of this
-    kernel, if it was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{dtype}.json")
+def measured_traffic(kernel: str, dtype: str, mode: str = "auto"):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's
+    readings) from the committed rocprofv3 counter summary of this kernel in
+    this execution mode, if it was taken on the current kernel sources; else
+    None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{dtype}_{mode}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -95,7 +97,7 @@ def kernel_table(plan, bufs):
 HBM_KERNELS = ("zero", "spread", "fft_x", "fft_y", "fft_z", "interp", "finalize", "transpose", "prephase")
 
 
-def roofline_entry(st, dtype, name=None, rows=1):
+def roofline_entry(st, dtype, name=None, rows=1, mode="auto"):
     """Roofline of one kernel (default: the one taking the most time): its
     algorithmic bytes (or VALU lane-operations) per launch over its average
     launch duration, against the MI355X peak."""
@@ -108,14 +110,14 @@ def roofline_entry(st, dtype, name=None, rows=1):
     if name in hbm_kernels:
         per_launch = v["alg_bytes"] / n
         achieved = per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
-        traffic = measured_traffic(name, dtype)
+        traffic = measured_traffic(name, dtype, mode)
         return name, {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
     # direct summation: VALU-bound; one term costs VALU_OPS_PER_TERM lane-operations
     ops = VALU_OPS_PER_TERM[(dtype, rows)]
     achieved = v["alg_flops"] / n * ops / avg_s / 1e12 if avg_s > 0 else 0.0
     return name, {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
-                  "frac": achieved / VALU_PEAK_TOPS, "traffic": None}
+                  "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(name, dtype, mode)}
 
 
 # VALU instructions issued per (target, source, data row) by the direct
@@ -306,9 +308,14 @@ def main():
             roofs = {}
             for k, v in r["stats"].items():
                 if v["launches"] and v["ms"] > 0 and (v["alg_bytes"] or k == "direct"):
-                    _, rf = roofline_entry(r["stats"], "f32", k, rows=rows)
+                    _, rf = roofline_entry(r["stats"], "f32", k, rows=rows, mode=m)
                     roofs[k] = {"bound": rf["bound"], "achieved": round(rf["achieved"], 1), "unit": rf["unit"],
                                 "frac": round(rf["frac"], 4)}
+                    if rf["traffic"]:
+                        # measured HBM bytes per launch over the launch duration
+                        avg_s = v["ms"] * 1e-3 / max(1, v["launches"])
+                        roofs[k]["traffic_GB_s"] = round(rf["traffic"] / avg_s / 1e9, 1)
+                        roofs[k]["traffic_frac"] = round(rf["traffic"] / avg_s / 1e9 / HBM_PEAK_GBS, 4)
             ent["rooflines"] = roofs
             out["modes"][m] = ent
     if args.serving:
