@@ -192,6 +192,9 @@ def main():
                     help="per-sub-problem NUFFT/direct choice: <0 automatic (default), 0 forced NUFFT, inf all direct")
     ap.add_argument("--serving", action="store_true", help="also run the 64-request serving workload (p50/p99)")
     ap.add_argument("--skip-f64", action="store_true", help="time the float32 plan only")
+    ap.add_argument("--n-pix", type=int, default=1000000,
+                    help="sky points of the SKA-like workload (default the full 1,000,000-point cap; smaller "
+                         "values only for counter runs, never for the reported metric)")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the forced-NUFFT and all-direct float32 runs reported beside the headline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -222,7 +225,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": nbytes, "copies": 3}), flush=True)
         return
-    wl = W.ska_like()
+    wl = W.ska_like(n_pix=args.n_pix)
     log(f"workload {wl.name}")
 
     def run_mode(dtype, eps, direct_threshold, steps, warm, ntrans=1):
@@ -279,7 +282,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "ska-like 995000 vis x 1000000 pix (200 antennas, 50 hour angles, "
+        "config": {"workload": f"ska-like {wl.n_vis} vis x {wl.n_pix} pix (200 antennas, 50 hour angles, "
                                "10-deg Fibonacci cap), synthesis+analysis", "eps": 1e-4,
                    "n_vis": wl.n_vis, "n_pix": wl.n_pix, "ntrans": 1},
         "roofline": roof,
