@@ -725,8 +725,8 @@ int make_host_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t 
     }
     floor_widths(Bw, Pw, p.sigma);
 
-    // Algorithm 1 + Algorithm 2 for the current kernel widths.
-    auto partition_domains = [&]() -> int {
+    // Algorithm 1 for the current kernel widths (sets hp->h, hp->eta).
+    auto size_boxes = [&]() -> int {
         // Algorithm 1 with the budget expressed as a Heisenberg volume: the two
         // grid buffers of a sub-problem hold ~ 2 prod(sigma h eta) cells of delta
         // bytes.  The padded sizes (kernel support, smooth FFT lengths, output
@@ -752,8 +752,11 @@ int make_host_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t 
             if (cur * shrink < floor_v) break;      // padding alone exceeds the budget: smallest boxes
             vmax = cur * shrink;
         }
-
-        // Algorithm 2 on both domains (or the caller's partitions)
+        return rc;
+    };
+    // Algorithm 2 on both domains (or the caller's partitions) for the current boxes.
+    auto partition_domains = [&]() -> int {
+        int rc = HVOX_OK;
         std::vector<int32_t> lv(n_vis), ls(n_pix);
         if (vis_chunk) std::copy(vis_chunk, vis_chunk + n_vis, lv.begin());
         else if (n_vis > 0) {
@@ -771,23 +774,48 @@ int make_host_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t 
         if (rc) return rc;
         return HVOX_OK;
     };
-    int rc = partition_domains();
-    if (rc) return rc;
     // Chunked evaluation sums K > 1 sub-problems into every output; their
     // errors add up (the paper notes the chunked result slightly misses eps
     // and suggests a smaller eps per sub-transform).  Reading: the kernels are
-    // sized for eps / min(4, K), then the partition is recomputed with them.
-    const int32_t K = std::max(hp->vis.nc, hp->sky.nc);
-    if (K > 1 && !p.all_direct && p.eps > 0.0) {
-        const double eps_sub = p.eps / std::min(4, K);
-        if (choose_kernels(&p, eps_sub) != HVOX_OK) {
-            *err = "no kernel for the per-sub-problem accuracy";
-            return HVOX_ERR_EPS;
+    // sized for eps / min(4, K^), K^ the number of lattice cells Algorithm 1's
+    // boxes cut the larger domain into (an upper bound on Algorithm 2's chunk
+    // count K), so the partition is computed once, with the final widths.
+    // (a caller's partition counts with its own number of chunks)
+    auto labels_count = [](const int32_t *lab, int64_t n) {
+        int32_t m = -1;
+        for (int64_t i = 0; i < n; ++i) m = std::max(m, lab[i]);
+        return static_cast<double>(m + 1);
+    };
+    const double kv_given = vis_chunk ? labels_count(vis_chunk, n_vis) : 0.0;
+    const double ks_given = sky_chunk ? labels_count(sky_chunk, n_pix) : 0.0;
+    auto lattice_cells = [&]() -> double {
+        double kv = 1.0, ks = 1.0;
+        for (int d = 0; d < 3; ++d) {
+            kv *= std::max(1.0, std::ceil(Bw[d] / hp->h[d]));
+            ks *= std::max(1.0, std::ceil(Pw[d] / hp->eta[d]));
         }
-        p.eps_sub = eps_sub;
-        rc = partition_domains();
-        if (rc) return rc;
+        return std::max(vis_chunk ? kv_given : kv, sky_chunk ? ks_given : ks);
+    };
+    int rc = size_boxes();
+    if (rc) return rc;
+    if (!p.all_direct && p.eps > 0.0) {
+        double kmin = 1.0;
+        for (int it = 0; it < 3; ++it) {
+            const double k = std::min(4.0, lattice_cells());
+            if (k <= kmin) break;
+            kmin = k;
+            const double eps_sub = p.eps / kmin;
+            if (choose_kernels(&p, eps_sub) != HVOX_OK) {
+                *err = "no kernel for the per-sub-problem accuracy";
+                return HVOX_ERR_EPS;
+            }
+            p.eps_sub = eps_sub;
+            rc = size_boxes();
+            if (rc) return rc;
+        }
     }
+    rc = partition_domains();
+    if (rc) return rc;
 
     // effective target half-widths: a dimension narrower than half a grid
     // cell against every source chunk is floored (its phase is negligible)
