@@ -31,8 +31,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Vector peaks from the unit counts and clock: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz = 39.3 T lane-cycles/s; float32 issues two lane-operations per
+# lane-cycle (157.3 TFLOP/s counting an FMA as 2 FLOP), float64 one (78.6).
+LANE_CYCLES_PER_S = 256 * 4 * 16 * 2.4e9
+VECTOR_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 METRIC = "(vis+pix)/s synth+analysis at eps=1e-4 FP32 vs 1e-9 FP64; p50/p99 latency"
 
 
@@ -113,11 +116,20 @@ def roofline_entry(st, dtype, name=None, rows=1, mode="auto"):
         traffic = measured_traffic(name, dtype, mode)
         return name, {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
-    # direct summation: VALU-bound; one term costs VALU_OPS_PER_TERM lane-operations
+    # direct summation: VALU-bound.  A term-row costs VALU_OPS_PER_TERM lane
+    # instructions, each counted as one FMA (2 FLOP) against the vector peak;
+    # issue_bound is the rate the instruction mix allows at the per-class
+    # issue rates (float32 arithmetic 2, float64 and the rest 1, hardware
+    # sine / cosine 1/2 per lane-cycle).
     ops = VALU_OPS_PER_TERM[(dtype, rows)]
-    achieved = v["alg_flops"] / n * ops / avg_s / 1e12 if avg_s > 0 else 0.0
-    return name, {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
-                  "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(name, dtype, mode)}
+    terms_per_s = v["alg_flops"] / n / avg_s if avg_s > 0 else 0.0
+    achieved = terms_per_s * ops * 2 / 1e12
+    peak = VECTOR_PEAK_TFLOPS[dtype]
+    bound = LANE_CYCLES_PER_S / VALU_CYCLES_PER_TERM[(dtype, rows)]
+    return name, {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                  "frac": achieved / peak, "traffic": measured_traffic(name, dtype, mode),
+                  "issue_bound": {"term_rows_per_s": bound, "achieved_term_rows_per_s": terms_per_s,
+                                  "frac": terms_per_s / bound}}
 
 
 # VALU instructions issued per (target, source, data row) by the direct
@@ -131,6 +143,13 @@ def roofline_entry(st, dtype, name=None, rows=1, mode="auto"):
 # the per-row multiply-accumulate.  Each is one lane-operation per lane.
 VALU_OPS_PER_TERM = {("f32", 1): 89 / 8, ("f32", 2): 62 / 8, ("f32", 3): 78 / 12, ("f32", 4): 94 / 16,
                      ("f64", 1): 203 / 6, ("f64", 2): 222 / 12, ("f64", 3): 245 / 18, ("f64", 4): 264 / 24}
+# Lane-cycles per term-row of the same loops at the per-class issue rates
+# (float32 arithmetic 1/2 cycle, hardware sine / cosine 2, the rest 1): float32
+# 1 row: 32 f32 + 16 transcendental + 41 other per 8 terms; 2 / 3 / 4 rows: 32 / 48
+# / 64 f32 + 8 transcendental + 22 other per 8 / 12 / 16 term-rows; float64 has no
+# float32 or transcendental instructions.
+VALU_CYCLES_PER_TERM = {("f32", 1): 89 / 8, ("f32", 2): 54 / 8, ("f32", 3): 62 / 12, ("f32", 4): 70 / 16,
+                        ("f64", 1): 203 / 6, ("f64", 2): 222 / 12, ("f64", 3): 245 / 18, ("f64", 4): 264 / 24}
 
 
 def cpu_baseline(wl, target_s=12.0):
@@ -314,6 +333,8 @@ def main():
                     _, rf = roofline_entry(r["stats"], "f32", k, rows=rows, mode=m)
                     roofs[k] = {"bound": rf["bound"], "achieved": round(rf["achieved"], 1), "unit": rf["unit"],
                                 "frac": round(rf["frac"], 4)}
+                    if "issue_bound" in rf:
+                        roofs[k]["issue_bound_frac"] = round(rf["issue_bound"]["frac"], 4)
                     if rf["traffic"]:
                         # measured HBM bytes per launch over the launch duration
                         avg_s = v["ms"] * 1e-3 / max(1, v["launches"])

@@ -158,7 +158,10 @@ int hvox_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t n_pix
               hvox_plan_t *out);
 
 /* sky -> vis:  vis[t][k] = sum_n sky[t][n] exp(-2 pi i <p_k, r_n>)   (Eq. 2)
- * sky: device [ntrans][n_pix] complex, vis: device [ntrans][n_vis] complex. */
+ * sky: device [ntrans][n_pix] complex, vis: device [ntrans][n_vis] complex.
+ * Rows are processed in groups of up to four: the direct sub-problems of a
+ * group share their phase factors across its rows (one kernel launch), the
+ * NUFFT sub-problems run row by row into the group's accumulator rows. */
 int hvox_synthesis(hvox_plan_t plan, const void *sky, void *vis, int32_t ntrans, void *stream);
 
 /* vis -> sky:  sky[t][n] = sum_k vis[t][k] exp(+2 pi i <p_k, r_n>)   (Eq. 3, the adjoint)
