@@ -192,33 +192,27 @@ __global__ void k_prephase(const PairDev *__restrict__ pairs, const int64_t *__r
     stage[g] = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
 }
 
-// One wavefront per grid-1 tile of kTileX x kTileY x kTileZ cells, held in
-// LDS (rows and planes padded by one cell so that neighbouring rows and planes
-// start on different banks).  The tile's sources (plan-time binning) are
-// staged kSpreadBatch at a time: pre-phased value, footprint origin, the
-// footprint clipped to the tile, and the 3w kernel values.  The wavefront then
-// takes the sources one by one and its lanes sweep the clipped footprint, x
-// fastest: within one source every lane updates a different cell, so the LDS
-// read-modify-writes need no atomics and the result is deterministic for a
-// plan.  The tile is written to grid 1 once, in full rows.  The tile's
-// sub-problem comes from a plan-time table, the values from the pre-phase pass.
+// One workgroup per grid-1 tile.  Thread (x, y) of the 32 x 8 face owns the
+// kTileZ cells of its column; the tile's sources are staged kSpreadBatch at a
+// time (their pre-phased values, footprint origin and 3w kernel values in
+// LDS), every thread adds the contributions that fall in its cells, and the
+// whole tile is written once (no atomics; for a given plan the result is
+// deterministic).  The tile's sub-problem comes from a plan-time table, its
+// source list from the plan-time binning, the values from the pre-phase pass.
 template <typename T>
-__global__ __launch_bounds__(64) void k_spread(const PairDev *__restrict__ pairs, const int32_t *__restrict__ tile_pair,
-                                               int64_t tile_base, const int64_t *__restrict__ pprefix,
-                                               const int64_t *__restrict__ tile_list,
-                                               const int64_t *__restrict__ toff,
-                                               const int32_t *__restrict__ records, const double *__restrict__ xyz,
-                                               int64_t nsrc, const cplx<T> *__restrict__ stage,
-                                               cplx<T> *__restrict__ ws, int w, T beta)
+__global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pairs, const int32_t *__restrict__ tile_pair,
+                                                int64_t tile_base, const int64_t *__restrict__ pprefix,
+                                                const int64_t *__restrict__ tile_list,
+                                                const int64_t *__restrict__ toff,
+                                                const int32_t *__restrict__ records, const double *__restrict__ xyz,
+                                                int64_t nsrc, const cplx<T> *__restrict__ stage,
+                                                cplx<T> *__restrict__ ws, int w, T beta)
 {
-    constexpr int kRow = kTileX + 1, kPlane = kRow * kTileY + 1;
-    __shared__ cplx<T> tile[kPlane * kTileZ];
     __shared__ T ker[kSpreadBatch][3 * kWMax];
     __shared__ T frac[kSpreadBatch][3];
     __shared__ cplx<T> val[kSpreadBatch];
-    __shared__ int box[kSpreadBatch][6];                   // clipped footprint: x0, y0, z0 (tile), ex, ey, ez
-    __shared__ int kof[kSpreadBatch][3];                   // kernel index of the clipped box's first cell
-    const int lane = threadIdx.x;
+    __shared__ int org[kSpreadBatch][3];
+    const int tid = threadIdx.x;
     const int64_t gt = tile_base + (tile_list ? tile_list[blockIdx.x] : (int64_t)blockIdx.x);
     const int p = tile_pair[gt];
     const int64_t r0 = toff[gt], r1 = toff[gt + 1];
@@ -228,67 +222,60 @@ __global__ __launch_bounds__(64) void k_spread(const PairDev *__restrict__ pairs
     const int ty = (int)((lt / P.ntile[0]) % P.ntile[1]);
     const int tz = (int)(lt / ((int64_t)P.ntile[0] * P.ntile[1]));
     const int ox = tx * kTileX, oy = ty * kTileY, oz = tz * kTileZ;
+    const int x = tid % kTileX, y = tid / kTileX;
     const T two_over_w = T(2) / T(w);
     const int w3 = 3 * w;
     const float rw = 1.0f / static_cast<float>(w), rw3 = 1.0f / static_cast<float>(w3);
     const cplx<T> *sv = stage + pprefix[p] - P.src_off;   // staged value of source n: sv[n]
-    for (int c = lane; c < kPlane * kTileZ; c += 64) tile[c] = mk<T>(T(0), T(0));
+    T accr[kTileZ], acci[kTileZ];
+#pragma unroll
+    for (int z = 0; z < kTileZ; ++z) accr[z] = acci[z] = T(0);
 
     for (int64_t base = r0; base < r1; base += kSpreadBatch) {
         const int cnt = (int)min((int64_t)kSpreadBatch, r1 - base);
         __syncthreads();
-        if (lane < cnt) {
-            const int64_t n = records[base + lane];
+        if (tid < cnt) {
+            const int64_t n = records[base + tid];
             double xp[3], t[3];
             int c0[3];
             source_footprint(P, xyz, nsrc, n, w, xp, t, c0);
-            const int o[3] = {c0[0] - ox, c0[1] - oy, c0[2] - oz};
-            const int tdim[3] = {kTileX, kTileY, kTileZ};
-            for (int d = 0; d < 3; ++d) {
-                frac[lane][d] = T((double)(c0[d] - P.n1[d] / 2) - t[d]);
-                const int lo = max(o[d], 0);
-                box[lane][d] = lo;
-                box[lane][3 + d] = max(0, min(o[d] + w, tdim[d]) - lo);
-                kof[lane][d] = lo - o[d];
-            }
-            val[lane] = sv[n];
+            for (int d = 0; d < 3; ++d) frac[tid][d] = T((double)(c0[d] - P.n1[d] / 2) - t[d]);
+            org[tid][0] = c0[0] - ox;
+            org[tid][1] = c0[1] - oy;
+            org[tid][2] = c0[2] - oz;
+            val[tid] = sv[n];
         }
         __syncthreads();
-        for (int i = lane; i < cnt * w3; i += 64) {
+        for (int i = tid; i < cnt * w3; i += 256) {
             const int j = small_div(i, rw3), r = i - __mul24(j, w3);
             const int d = small_div(r, rw), q = r - __mul24(d, w);
             ker[j][r] = es_kernel((frac[j][d] + T(q)) * two_over_w, beta);
         }
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
-            const int ex = box[j][3], ey = box[j][4], ez = box[j][5];
-            const int total = ex * ey * ez;
-            if (total == 0) continue;
-            const float rex = 1.0f / static_cast<float>(ex), rey = 1.0f / static_cast<float>(ey);
-            const cplx<T> vj = val[j];
-            const T *kx = ker[j] + kof[j][0], *ky = ker[j] + w + kof[j][1], *kz = ker[j] + 2 * w + kof[j][2];
-            const int base_cell = box[j][2] * kPlane + box[j][1] * kRow + box[j][0];
-            for (int c = lane; c < total; c += 64) {
-                const int yz = small_div(c, rex), ix = c - __mul24(yz, ex);
-                const int iz = small_div(yz, rey), iy = yz - __mul24(iz, ey);
-                const T wgt = kx[ix] * ky[iy] * kz[iz];
-                const int cell = base_cell + iz * kPlane + iy * kRow + ix;
-                cplx<T> g = tile[cell];
-                g.x += vj.x * wgt;
-                g.y += vj.y * wgt;
-                tile[cell] = g;
+            const int qx = x - org[j][0], qy = y - org[j][1];
+            if ((unsigned)qx >= (unsigned)w || (unsigned)qy >= (unsigned)w) continue;
+            const T kxy = ker[j][qx] * ker[j][w + qy];
+            const T vr = val[j].x * kxy, vi = val[j].y * kxy;
+            const int oz0 = org[j][2];
+#pragma unroll
+            for (int z = 0; z < kTileZ; ++z) {
+                const int qz = z - oz0;
+                if ((unsigned)qz < (unsigned)w) {
+                    const T kz = ker[j][2 * w + qz];
+                    accr[z] += vr * kz;
+                    acci[z] += vi * kz;
+                }
             }
         }
     }
-    __syncthreads();
-    const int gx = ox + (lane & (kTileX - 1));
-    if (gx < P.n1[0]) {
+    const int gx = ox + x, gy = oy + y;
+    if (gx < P.n1[0] && gy < P.n1[1]) {
         cplx<T> *grid = ws + P.bufG;
-        for (int r = lane >> 5; r < kTileY * kTileZ; r += 2) {   // two rows of 32 cells per pass
-            const int y = r % kTileY, z = r / kTileY;
-            const int gy = oy + y, gz = oz + z;
-            if (gy < P.n1[1] && gz < P.n1[2])
-                grid[((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx] = tile[z * kPlane + y * kRow + (lane & (kTileX - 1))];
+#pragma unroll
+        for (int z = 0; z < kTileZ; ++z) {
+            const int gz = oz + z;
+            if (gz < P.n1[2]) grid[((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx] = mk<T>(accr[z], acci[z]);
         }
     }
 }
@@ -885,7 +872,7 @@ hipError_t launch_spread(const PairDev *pairs, const int32_t *tile_pair, int64_t
                          hipStream_t st)
 {
     if (tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spread<T>, dim3(static_cast<unsigned>(tiles)), dim3(64), 0, st, pairs, tile_pair, tile_base,
+    hipLaunchKernelGGL(k_spread<T>, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, st, pairs, tile_pair, tile_base,
                        pprefix, tile_list, toff, records, xyz, nsrc, static_cast<const cplx<T> *>(stage),
                        static_cast<cplx<T> *>(ws), w, T(beta));
     return hipGetLastError();
