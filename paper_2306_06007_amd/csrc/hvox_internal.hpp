@@ -39,11 +39,11 @@ constexpr int kMaxStages = 16;       // radix stages per FFT length
 // workgroups per launch of the kernels whose grid grows with the problem (direct,
 // interp): a dispatch counts its work-items in 32 bits
 constexpr int64_t kMaxLaunchBlocks = int64_t(1) << 22;
-// spreading by grid-1 tile: one wavefront per tile of kTileX x kTileY x
-// kTileZ cells, a column of kTileZ cells per lane; points touching the tile
-// are staged up to kSpreadBatch (<= 64) at a time
-constexpr int kTileX = 8, kTileY = 8, kTileZ = 8;
-constexpr int kSpreadBatch = 32;
+// spreading by grid-1 tile: one 256-thread workgroup per tile of
+// kTileX x kTileY x kTileZ cells, a column of kTileZ cells per thread; points
+// touching the tile are staged kSpreadBatch at a time
+constexpr int kTileX = 32, kTileY = 8, kTileZ = 8;
+constexpr int kSpreadBatch = 64;
 
 // ---- one type-3 sub-problem (source chunk -> target chunk) on the device ---
 // FFT passes: x reads grid 1 (contiguous lines) and writes its kept window

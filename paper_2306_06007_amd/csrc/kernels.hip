@@ -192,32 +192,27 @@ __global__ void k_prephase(const PairDev *__restrict__ pairs, const int64_t *__r
     stage[g] = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
 }
 
-// One wavefront per grid-1 tile of kTileX x kTileY x kTileZ = 8 x 8 x 8
-// cells: lane (x, y) owns the kTileZ cells of its column in registers.  The
-// tile's sources (plan-time binning) are staged in LDS (pre-phased value,
-// footprint origin, the 3w kernel values); for every source the lanes inside
-// its footprint add their column's contributions.  An 8 x 8 face keeps most
-// lanes inside a source's w x w footprint, and the per-source z range is
-// uniform across the wavefront.  The tile is written to grid 1 once (no
-// atomics: for a given plan the result is deterministic).  The tile's
-// sub-problem comes from a plan-time table, the values from the pre-phase pass.
+// One workgroup per grid-1 tile.  Thread (x, y) of the 32 x 8 face owns the
+// kTileZ cells of its column; the tile's sources are staged kSpreadBatch at a
+// time (their pre-phased values, footprint origin and 3w kernel values in
+// LDS), every thread adds the contributions that fall in its cells, and the
+// whole tile is written once (no atomics; for a given plan the result is
+// deterministic).  The tile's sub-problem comes from a plan-time table, its
+// source list from the plan-time binning, the values from the pre-phase pass.
 template <typename T>
-__global__ __launch_bounds__(64) void k_spread(const PairDev *__restrict__ pairs, const int32_t *__restrict__ tile_pair,
-                                               int64_t tile_base, const int64_t *__restrict__ pprefix,
-                                               const int64_t *__restrict__ tile_list,
-                                               const int64_t *__restrict__ toff,
-                                               const int32_t *__restrict__ records, const double *__restrict__ xyz,
-                                               int64_t nsrc, const cplx<T> *__restrict__ stage,
-                                               cplx<T> *__restrict__ ws, int w, T beta)
+__global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pairs, const int32_t *__restrict__ tile_pair,
+                                                int64_t tile_base, const int64_t *__restrict__ pprefix,
+                                                const int64_t *__restrict__ tile_list,
+                                                const int64_t *__restrict__ toff,
+                                                const int32_t *__restrict__ records, const double *__restrict__ xyz,
+                                                int64_t nsrc, const cplx<T> *__restrict__ stage,
+                                                cplx<T> *__restrict__ ws, int w, T beta)
 {
-    static_assert(kTileX == 8 && kTileY == 8, "one lane per (x, y) column of the tile face");
-    constexpr int kKer = 48;                               // kernel values held per staged source
-    __shared__ T ker[kSpreadBatch * kKer];
+    __shared__ T ker[kSpreadBatch][3 * kWMax];
     __shared__ T frac[kSpreadBatch][3];
     __shared__ cplx<T> val[kSpreadBatch];
     __shared__ int org[kSpreadBatch][3];
-    const int lane = threadIdx.x;
-    const int x = lane & 7, y = lane >> 3;
+    const int tid = threadIdx.x;
     const int64_t gt = tile_base + (tile_list ? tile_list[blockIdx.x] : (int64_t)blockIdx.x);
     const int p = tile_pair[gt];
     const int64_t r0 = toff[gt], r1 = toff[gt + 1];
@@ -227,48 +222,47 @@ __global__ __launch_bounds__(64) void k_spread(const PairDev *__restrict__ pairs
     const int ty = (int)((lt / P.ntile[0]) % P.ntile[1]);
     const int tz = (int)(lt / ((int64_t)P.ntile[0] * P.ntile[1]));
     const int ox = tx * kTileX, oy = ty * kTileY, oz = tz * kTileZ;
+    const int x = tid % kTileX, y = tid / kTileX;
     const T two_over_w = T(2) / T(w);
     const int w3 = 3 * w;
-    const int per_round = min(kSpreadBatch, (kSpreadBatch * kKer) / w3);   // sources staged per round
     const float rw = 1.0f / static_cast<float>(w), rw3 = 1.0f / static_cast<float>(w3);
     const cplx<T> *sv = stage + pprefix[p] - P.src_off;   // staged value of source n: sv[n]
     T accr[kTileZ], acci[kTileZ];
 #pragma unroll
     for (int z = 0; z < kTileZ; ++z) accr[z] = acci[z] = T(0);
 
-    for (int64_t base = r0; base < r1; base += per_round) {
-        const int cnt = (int)min((int64_t)per_round, r1 - base);
+    for (int64_t base = r0; base < r1; base += kSpreadBatch) {
+        const int cnt = (int)min((int64_t)kSpreadBatch, r1 - base);
         __syncthreads();
-        if (lane < cnt) {
-            const int64_t n = records[base + lane];
+        if (tid < cnt) {
+            const int64_t n = records[base + tid];
             double xp[3], t[3];
             int c0[3];
             source_footprint(P, xyz, nsrc, n, w, xp, t, c0);
-            for (int d = 0; d < 3; ++d) frac[lane][d] = T((double)(c0[d] - P.n1[d] / 2) - t[d]);
-            org[lane][0] = c0[0] - ox;
-            org[lane][1] = c0[1] - oy;
-            org[lane][2] = c0[2] - oz;
-            val[lane] = sv[n];
+            for (int d = 0; d < 3; ++d) frac[tid][d] = T((double)(c0[d] - P.n1[d] / 2) - t[d]);
+            org[tid][0] = c0[0] - ox;
+            org[tid][1] = c0[1] - oy;
+            org[tid][2] = c0[2] - oz;
+            val[tid] = sv[n];
         }
         __syncthreads();
-        for (int i = lane; i < cnt * w3; i += 64) {
+        for (int i = tid; i < cnt * w3; i += 256) {
             const int j = small_div(i, rw3), r = i - __mul24(j, w3);
             const int d = small_div(r, rw), q = r - __mul24(d, w);
-            ker[j * w3 + r] = es_kernel((frac[j][d] + T(q)) * two_over_w, beta);
+            ker[j][r] = es_kernel((frac[j][d] + T(q)) * two_over_w, beta);
         }
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
             const int qx = x - org[j][0], qy = y - org[j][1];
             if ((unsigned)qx >= (unsigned)w || (unsigned)qy >= (unsigned)w) continue;
-            const T *kj = ker + j * w3;
-            const T kxy = kj[qx] * kj[w + qy];
+            const T kxy = ker[j][qx] * ker[j][w + qy];
             const T vr = val[j].x * kxy, vi = val[j].y * kxy;
-            const int oz0 = __builtin_amdgcn_readfirstlane(org[j][2]);   // the same for every lane
+            const int oz0 = org[j][2];
 #pragma unroll
             for (int z = 0; z < kTileZ; ++z) {
                 const int qz = z - oz0;
                 if ((unsigned)qz < (unsigned)w) {
-                    const T kz = kj[2 * w + qz];
+                    const T kz = ker[j][2 * w + qz];
                     accr[z] += vr * kz;
                     acci[z] += vi * kz;
                 }
@@ -878,7 +872,7 @@ hipError_t launch_spread(const PairDev *pairs, const int32_t *tile_pair, int64_t
                          hipStream_t st)
 {
     if (tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spread<T>, dim3(static_cast<unsigned>(tiles)), dim3(64), 0, st, pairs, tile_pair, tile_base,
+    hipLaunchKernelGGL(k_spread<T>, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, st, pairs, tile_pair, tile_base,
                        pprefix, tile_list, toff, records, xyz, nsrc, static_cast<const cplx<T> *>(stage),
                        static_cast<cplx<T> *>(ws), w, T(beta));
     return hipGetLastError();
