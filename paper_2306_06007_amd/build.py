@@ -38,7 +38,7 @@ def build(verbose: bool = False) -> str:
             _run([hipcc] + COMMON + extra + ["-c", os.path.join(CSRC, src), "-o", obj], verbose)
             objs.append(obj)
         out_tmp = LIB + ".tmp"
-        _run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", out_tmp] + objs, verbose)
+        _run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-o", out_tmp] + objs, verbose)
         os.replace(out_tmp, LIB)
     return LIB
 

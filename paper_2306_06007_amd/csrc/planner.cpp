@@ -14,6 +14,8 @@
 #include <limits>
 #include <map>
 #include <numeric>
+#include <string>
+#include <thread>
 #include <unordered_map>
 
 #include "hvox_internal.hpp"
@@ -755,23 +757,26 @@ int make_host_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t 
         return rc;
     };
     // Algorithm 2 on both domains (or the caller's partitions) for the current boxes.
+    // The two domains are independent: the sky is partitioned on a second
+    // host thread while this one partitions the visibilities.
     auto partition_domains = [&]() -> int {
-        int rc = HVOX_OK;
-        std::vector<int32_t> lv(n_vis), ls(n_pix);
-        if (vis_chunk) std::copy(vis_chunk, vis_chunk + n_vis, lv.begin());
-        else if (n_vis > 0) {
-            int64_t nc = partition(uvw, n_vis, hp->h, lv.data());
-            if (nc < 0) { *err = "Algorithm 2 failed on the visibilities"; return static_cast<int>(nc); }
-        }
-        if (sky_chunk) std::copy(sky_chunk, sky_chunk + n_pix, ls.begin());
-        else if (n_pix > 0) {
-            int64_t nc = partition(xyz, n_pix, hp->eta, ls.data());
-            if (nc < 0) { *err = "Algorithm 2 failed on the sky"; return static_cast<int>(nc); }
-        }
-        rc = build_chunkset(uvw, n_vis, lv.data(), &hp->vis, err);
-        if (rc) return rc;
-        rc = build_chunkset(xyz, n_pix, ls.data(), &hp->sky, err);
-        if (rc) return rc;
+        auto one = [](const double *pts, int64_t n, const int32_t *given, const double *box, ChunkSet *out,
+                      std::string *msg, const char *what) -> int {
+            std::vector<int32_t> lab(n);
+            if (given) std::copy(given, given + n, lab.begin());
+            else if (n > 0) {
+                int64_t nc = partition(pts, n, box, lab.data());
+                if (nc < 0) { *msg = std::string("Algorithm 2 failed on the ") + what; return static_cast<int>(nc); }
+            }
+            return build_chunkset(pts, n, lab.data(), out, msg);
+        };
+        std::string err_sky;
+        int rc_sky = HVOX_OK;
+        std::thread sky([&] { rc_sky = one(xyz, n_pix, sky_chunk, hp->eta, &hp->sky, &err_sky, "sky"); });
+        const int rc_vis = one(uvw, n_vis, vis_chunk, hp->h, &hp->vis, err, "visibilities");
+        sky.join();
+        if (rc_vis) return rc_vis;
+        if (rc_sky) { *err = err_sky; return rc_sky; }
         return HVOX_OK;
     };
     // Chunked evaluation sums K > 1 sub-problems into every output; their
