@@ -135,23 +135,21 @@ def roofline_entry(st, dtype, name=None, rows=1, mode="auto"):
 
 
 # VALU instructions issued per (target, source, data row) by the direct
-# kernel's inner loop, counted from its gfx950 assembly (LDS reads and scalar
-# loop control excluded), by plan precision and rows per launch.  Float32: per
-# unrolled iteration of 4 sources x 2 targets (1 row) or 2 x 2 (2-4 rows), the
-# float64 dot product and fractional part, the conversion, hardware sine and
-# cosine (shared by the rows) and one complex multiply-accumulate per row;
-# float64: per iteration of 3 sources x 2 targets, the float64 dot product,
-# quarter-turn reduction, Maclaurin sine and cosine and rotation (shared) and
-# the per-row multiply-accumulate.  Each is one lane-operation per lane.
-VALU_OPS_PER_TERM = {("f32", 1): 89 / 8, ("f32", 2): 62 / 8, ("f32", 3): 78 / 12, ("f32", 4): 94 / 16,
-                     ("f64", 1): 203 / 6, ("f64", 2): 222 / 12, ("f64", 3): 245 / 18, ("f64", 4): 264 / 24}
+# kernel's inner loop, counted from its gfx950 assembly (the loop that reads
+# the staged sources from LDS; LDS reads and scalar loop control excluded), by
+# plan precision and rows per launch.  Per iteration of 4 sources x 2 targets:
+# the float64 dot product and reduction to a fraction of a turn (shared by the
+# rows), float32: conversion and hardware sine and cosine (shared), float64:
+# Maclaurin sine and cosine and quarter-turn rotation (shared), then one
+# complex multiply-accumulate per row.  Each is one lane-operation per lane.
+VALU_OPS_PER_TERM = {("f32", 1): 89 / 8, ("f32", 2): 121 / 16, ("f32", 3): 153 / 24, ("f32", 4): 185 / 32,
+                     ("f64", 1): 338 / 8, ("f64", 2): 370 / 16, ("f64", 3): 402 / 24, ("f64", 4): 434 / 32}
 # Lane-cycles per term-row of the same loops at the per-class issue rates
 # (float32 arithmetic 1/2 cycle, hardware sine / cosine 2, the rest 1): float32
-# 1 row: 32 f32 + 16 transcendental + 41 other per 8 terms; 2 / 3 / 4 rows: 32 / 48
-# / 64 f32 + 8 transcendental + 22 other per 8 / 12 / 16 term-rows; float64 has no
-# float32 or transcendental instructions.
-VALU_CYCLES_PER_TERM = {("f32", 1): 89 / 8, ("f32", 2): 54 / 8, ("f32", 3): 62 / 12, ("f32", 4): 70 / 16,
-                        ("f64", 1): 203 / 6, ("f64", 2): 222 / 12, ("f64", 3): 245 / 18, ("f64", 4): 264 / 24}
+# 32 / 64 / 96 / 128 float32 + 16 transcendental + 41 other per 8 / 16 / 24 / 32
+# term-rows; float64 has no float32 or transcendental instructions.
+VALU_CYCLES_PER_TERM = {("f32", 1): 89 / 8, ("f32", 2): 105 / 16, ("f32", 3): 121 / 24, ("f32", 4): 137 / 32,
+                        ("f64", 1): 338 / 8, ("f64", 2): 370 / 16, ("f64", 3): 402 / 24, ("f64", 4): 434 / 32}
 
 
 def cpu_baseline(wl, target_s=12.0):

@@ -696,8 +696,10 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
 //   s_k.x_n = s_k.x_S + s_T.(x_n - x_S) + (s_k - s_T).(x_n - x_S):
 // the first two terms are evaluated once per (target, tile) and
 // (source, tile); only the small third term is evaluated per (target,
-// source) pair.  The sign iota is folded into the staged values
-// (c exp(-i t) = conj(conj(c) exp(+i t))), so the inner loop always
+// source) pair.  Every phase is reduced to [-1/2, 1/2) turn in float64 and
+// its sine / cosine taken in the plan's precision (cis_rev).  The sign iota
+// is folded into the staged values (c exp(-i t) = conj(conj(c) exp(+i t))),
+// so the inner loop always
 // accumulates c exp(+2 pi i t).  Phases are float64 (full rate on CDNA).
 // ---------------------------------------------------------------------------
 
@@ -746,18 +748,20 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__r
             lx[tid] = dxv[0];
             ly[tid] = dxv[1];
             lz[tid] = dxv[2];
-            const double2 e = cis_cycles(ph, iota);
+            T ec, es;
+            cis_rev(iota * ph, ec, es);   // exp(2 pi i iota ph): float64 reduction, plan-precision sine / cosine
             const int64_t u = perm[n];
 #pragma unroll
             for (int r = 0; r < NT; ++r) {
                 const cplx<T> c = in[r * in_stride + u];
-                lc[r][tid] = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
+                lc[r][tid] = mk<T>(c.x * ec - c.y * es, c.x * es + c.y * ec);
             }
         }
         __syncthreads();
         T b0r[NT], b0i[NT], b1r[NT], b1i[NT];
 #pragma unroll
         for (int r = 0; r < NT; ++r) b0r[r] = b0i[r] = b1r[r] = b1i[r] = T(0);
+#pragma unroll 4
         for (int j = 0; j < cnt; ++j) {
             const double xj = lx[j], yj = ly[j], zj = lz[j];
             const double t0 = fma(sp0[0], xj, fma(sp0[1], yj, sp0[2] * zj));
@@ -780,7 +784,10 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__r
             ph0 += sk0[d] * xS[d];
             ph1 += sk1[d] * xS[d];
         }
-        const double2 e0 = cis_cycles(ph0, iota), e1 = cis_cycles(ph1, iota);
+        T e0c, e0s, e1c, e1s;
+        cis_rev(iota * ph0, e0c, e0s);
+        cis_rev(iota * ph1, e1c, e1s);
+        const double2 e0 = make_double2(e0c, e0s), e1 = make_double2(e1c, e1s);
 #pragma unroll
         for (int r = 0; r < NT; ++r) {
             a0r[r] += (double)b0r[r] * e0.x - (double)b0i[r] * e0.y;
