@@ -25,10 +25,9 @@ hipError_t launch_bin(const PairDev *pairs, const int64_t *prefix, int npairs, i
                       hipStream_t st);
 template <typename T>
 hipError_t launch_prephase(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t, const int32_t *,
-                           const void *, void *, double, hipStream_t);
+                           const void *, void *, double, int, hipStream_t);
 template <typename T>
-hipError_t launch_spread(const PairDev *, const int32_t *, int64_t, const int64_t *, int64_t, const int64_t *,
-                         const int64_t *, const int32_t *, const double *, int64_t, const void *, void *, int, double,
+hipError_t launch_spread(const PairDev *, const SpreadTile *, int64_t, const int32_t *, const void *, void *, int, double,
                          hipStream_t);
 template <typename T>
 hipError_t launch_fft(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *, const void *, int,
@@ -61,10 +60,8 @@ struct DevDir {
     double *deconv = nullptr;        // per chunk-order target
     int64_t *pre_stiles = nullptr;   // per batch: tile prefix over its pairs
     int64_t *pre_ttiles = nullptr;   // per batch: transpose-tile prefix over its pairs
-    int64_t *tile_off = nullptr;     // [tiles_total + 1] record offsets of every grid-1 tile
     int32_t *records = nullptr;      // source indices listed per tile (plan-resident binning)
-    int64_t *tile_list = nullptr;    // non-empty tiles of sparse batches (batch-local indices)
-    int32_t *tile_pair = nullptr;    // [tiles_total] sub-problem of every grid-1 tile (index within its batch)
+    SpreadTile *spread_tiles = nullptr;   // spreading tiles of every batch (descriptor per workgroup)
 };
 
 struct TimedLaunch {
@@ -87,7 +84,7 @@ struct hvox_plan_s {
     void *tw = nullptr;
     hvox::DevDir syn, ana;
     void *ws = nullptr;
-    void *stage = nullptr;                              // pre-phased source values of one batch
+    void *stage = nullptr;                              // staged sources of one batch (value and footprint)
     double *acc = nullptr;
     hipStream_t last_stream = nullptr;
     double plan_seconds = 0.0;
@@ -234,10 +231,9 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
                 const PairDev *pairs = dd.pairs + b.pair0;
                 const int np = static_cast<int>(b.npairs);
                 const int64_t *pprefix = dd.pre_pts + b.pre_pts;
-                const int64_t tile_base = dp.pairs[b.pair0].tile0;
                 HVOX_TRY(timed(pl, HVOX_K_PREPHASE, st, [&] {
                     return launch_prephase<T>(pairs, pprefix, np, b.pts, sxyz, n_src, sperm, in_t, pl->stage, iota,
-                                              st);
+                                              p.w, st);
                 }));
                 if (b.sparse) {
                     // mostly empty grid 1: clear the batch's grid-1 region, then spread the listed tiles
@@ -245,18 +241,11 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
                         return launch_zero(static_cast<double *>(pl->ws),
                                            b.g_cnt * static_cast<int64_t>(sizeof(C) / sizeof(double)), st);
                     }));
-                    HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
-                        return launch_spread<T>(pairs, dd.tile_pair, tile_base, pprefix, b.list_cnt,
-                                                dd.tile_list + b.list_off, dd.tile_off, dd.records, sxyz, n_src,
-                                                pl->stage, pl->ws, p.w, p.beta, st);
-                    }));
-                } else {
-                    HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
-                        return launch_spread<T>(pairs, dd.tile_pair, tile_base, pprefix, b.stiles, nullptr,
-                                                dd.tile_off, dd.records, sxyz, n_src, pl->stage, pl->ws, p.w, p.beta,
-                                                st);
-                    }));
                 }
+                HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
+                    return launch_spread<T>(pairs, dd.spread_tiles + b.list_off, b.list_cnt, dd.records, pl->stage,
+                                            pl->ws, p.w, p.beta, st);
+                }));
                 for (int pass = 0; pass < 3; ++pass) {
                     HVOX_TRY(timed(pl, HVOX_K_FFT_X + pass, st, [&] {
                         return launch_fft<T>(pairs, dd.pre_tiles[pass] + b.pre_tiles[pass], np, b.tiles[pass], pass,
@@ -360,62 +349,57 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
     if (e != hipSuccess) return bad(e, "binning count pass");
     std::vector<int64_t> off(nt + 1, 0);
     for (int64_t i = 0; i < nt; ++i) off[i + 1] = off[i] + counts[i];
-    // batches whose grid 1 is mostly empty: clear it with one fill, spread only the non-empty tiles
-    dp.tile_list.clear();
+    // batches whose grid 1 is mostly empty: clear it with one fill, spread only
+    // the non-empty tiles; other batches spread every tile (empty ones write zeros)
+    dp.spread_tiles.clear();
     const double delta = pl->hp.prm.dtype == HVOX_F64 ? 16.0 : 8.0;
     for (Batch &b : dp.batches) {
         const int64_t t0 = dp.pairs[b.pair0].tile0;
         int64_t nonempty = 0;
         for (int64_t t = 0; t < b.stiles; ++t) nonempty += counts[t0 + t] > 0;
         b.sparse = 2 * nonempty < b.stiles;
-        b.list_off = static_cast<int64_t>(dp.tile_list.size());
-        b.list_cnt = 0;
-        if (!b.sparse) continue;
-        // the fill writes the batch's grid-1 region, spreading only the listed tiles' cells
+        b.list_off = static_cast<int64_t>(dp.spread_tiles.size());
         double listed_cells = 0.0;
         for (int64_t i = 0; i < b.npairs; ++i) {
             const PairDev &pd = dp.pairs[b.pair0 + i];
-            const int64_t nt = static_cast<int64_t>(pd.ntile[0]) * pd.ntile[1] * pd.ntile[2];
-            for (int64_t lt = 0; lt < nt; ++lt) {
-                if (counts[pd.tile0 + lt] == 0) continue;
-                dp.tile_list.push_back(pd.tile0 + lt - t0);
-                const int64_t tx = lt % pd.ntile[0], ty = (lt / pd.ntile[0]) % pd.ntile[1];
-                const int64_t tz = lt / (static_cast<int64_t>(pd.ntile[0]) * pd.ntile[1]);
-                listed_cells += static_cast<double>(std::min<int64_t>(kTileX, pd.n1[0] - tx * kTileX)) *
-                                std::min<int64_t>(kTileY, pd.n1[1] - ty * kTileY) *
-                                std::min<int64_t>(kTileZ, pd.n1[2] - tz * kTileZ);
-            }
+            int64_t gt = pd.tile0;   // tiles are numbered x fastest, then y, then z
+            for (int32_t tz = 0; tz < pd.ntile[2]; ++tz)
+                for (int32_t ty = 0; ty < pd.ntile[1]; ++ty)
+                    for (int32_t tx = 0; tx < pd.ntile[0]; ++tx, ++gt) {
+                        if (b.sparse && counts[gt] == 0) continue;
+                        SpreadTile d{};
+                        d.r0 = off[gt];
+                        d.cnt = counts[gt];
+                        d.pair = static_cast<int32_t>(i);
+                        d.org[0] = static_cast<int16_t>(tx * kTileX);
+                        d.org[1] = static_cast<int16_t>(ty * kTileY);
+                        d.org[2] = static_cast<int16_t>(tz * kTileZ);
+                        dp.spread_tiles.push_back(d);
+                        listed_cells += static_cast<double>(std::min(kTileX, pd.n1[0] - tx * kTileX)) *
+                                        std::min(kTileY, pd.n1[1] - ty * kTileY) *
+                                        std::min(kTileZ, pd.n1[2] - tz * kTileZ);
+                    }
         }
-        b.list_cnt = static_cast<int64_t>(dp.tile_list.size()) - b.list_off;
+        b.list_cnt = static_cast<int64_t>(dp.spread_tiles.size()) - b.list_off;
+        if (!b.sparse) continue;
+        // the fill writes the batch's grid-1 region, spreading only the listed tiles' cells
         dp.alg_bytes[HVOX_K_SPREAD] -= delta * (static_cast<double>(b.g_cnt) - listed_cells);
         dp.alg_bytes[HVOX_K_ZERO] += delta * static_cast<double>(b.g_cnt);
     }
-    if (!dp.tile_list.empty()) {
-        hipError_t el = upload(pl, dp.tile_list, &dd->tile_list, st);
-        if (el != hipSuccess) return bad(el, "tile list");
+    if (!dp.spread_tiles.empty()) {
+        hipError_t el = upload(pl, dp.spread_tiles, &dd->spread_tiles, st);
+        if (el == hipSuccess) el = hipStreamSynchronize(st);
+        if (el != hipSuccess) return bad(el, "spreading tiles");
+        dp.spread_tiles.clear();
+        dp.spread_tiles.shrink_to_fit();
     }
-    {
-        // sub-problem of every tile, as an index into its batch's pairs
-        std::vector<int32_t> tp(nt);
-        for (const Batch &b : dp.batches)
-            for (int64_t i = 0; i < b.npairs; ++i) {
-                const PairDev &pd = dp.pairs[b.pair0 + i];
-                const int64_t n_tiles = static_cast<int64_t>(pd.ntile[0]) * pd.ntile[1] * pd.ntile[2];
-                std::fill(tp.begin() + pd.tile0, tp.begin() + pd.tile0 + n_tiles, static_cast<int32_t>(i));
-            }
-        hipError_t el = upload(pl, tp, &dd->tile_pair, st);
-        if (el == hipSuccess) el = hipStreamSynchronize(st);   // tp is released on return
-        if (el != hipSuccess) return bad(el, "tile table");
-    }
-    e = upload(pl, off, &dd->tile_off, st);
-    if (e != hipSuccess) return bad(e, "tile offsets");
     void *rec = nullptr;
     e = dev_alloc(pl, sizeof(int32_t) * std::max<int64_t>(off[nt], 1), &rec, true);
     if (e != hipSuccess) return bad(e, "tile records");
     dd->records = static_cast<int32_t *>(rec);
     e = hipMalloc(&d_cursor, sizeof(unsigned long long) * nt);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(d_cursor, dd->tile_off, sizeof(int64_t) * nt, hipMemcpyDeviceToDevice, st);
+        e = hipMemcpyAsync(d_cursor, off.data(), sizeof(int64_t) * nt, hipMemcpyHostToDevice, st);
     for (const Batch &b : dp.batches) {
         if (e != hipSuccess) break;
         e = launch_bin(dd->pairs + b.pair0, dd->pre_pts + b.pre_pts, static_cast<int>(b.npairs), b.pts, sxyz, n_src,
@@ -543,7 +527,8 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
     int64_t max_pts = 0;
     for (const DirPlan *dp : {&hp.syn, &hp.ana})
         for (const Batch &b : dp->batches) max_pts = std::max(max_pts, b.pts);
-    if (max_pts > 0) chk(dev_alloc(pl, delta * static_cast<size_t>(max_pts), &pl->stage, true), "source staging");
+    const size_t staged = p.dtype == HVOX_F64 ? sizeof(StagedSrc<double>) : sizeof(StagedSrc<float>);
+    if (max_pts > 0) chk(dev_alloc(pl, staged * static_cast<size_t>(max_pts), &pl->stage, true), "source staging");
     if (rc) return rc;
     chk(hipStreamSynchronize(st), "plan upload");
     return rc;

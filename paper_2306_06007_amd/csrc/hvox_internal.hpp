@@ -44,6 +44,21 @@ constexpr int64_t kMaxLaunchBlocks = int64_t(1) << 22;
 // touching the tile are staged kSpreadBatch at a time
 constexpr int kTileX = 32, kTileY = 8, kTileZ = 8;
 constexpr int kSpreadBatch = 64;
+// sources of one batch of sub-problems (bounds the staging buffer; staged
+// indices fit 32 bits)
+constexpr int64_t kMaxBatchPts = int64_t(1) << 25;
+
+// A source of a NUFFT sub-problem as the pre-phase pass leaves it for the
+// spreading kernel: the pre-phased value, and the footprint of its kernel on
+// grid 1 (first cell c0 per dimension and the offset frac = (c0 - n1/2) - t of
+// that cell from the source's grid-1 coordinate t, in the plan's precision).
+template <typename T>
+struct alignas(16) StagedSrc {
+    T v[2];
+    T frac[3];
+    int32_t c0[3];
+};
+static_assert(sizeof(StagedSrc<float>) == 32 && sizeof(StagedSrc<double>) == 64, "staged source layout");
 
 // ---- one type-3 sub-problem (source chunk -> target chunk) on the device ---
 // FFT passes: x reads grid 1 (contiguous lines) and writes its kept window
@@ -83,6 +98,19 @@ struct PairDev {
     uint8_t radix[3][kMaxStages];
 };
 
+// ---- one grid-1 tile of a batch handed to the spreading kernel ------------
+// Plan-time descriptor: a single load gives the workgroup its sub-problem,
+// its cells and its source list.
+struct SpreadTile {
+    int64_t r0;                  // first of the tile's records (source indices) in the direction's list
+    int32_t cnt;                 // records of the tile
+    int32_t pair;                // sub-problem, as an index into its batch's pairs
+    int16_t org[3];              // grid-1 cell of the tile's first corner
+    int16_t pad_;
+};
+static_assert(sizeof(SpreadTile) == 24, "spreading tile descriptor layout");
+static_assert(kFftMaxLen < 32768, "tile corners are stored in 16 bits");
+
 // ---- direct-sum work item: <= kDirectTile targets x <= kDirectSeg sources --
 struct DirectItem {
     int64_t tgt_off;             // chunk-order index of the first target
@@ -112,7 +140,8 @@ struct Batch {
     int64_t ttiles = 0;                  // transpose tiles (workgroups)
     int64_t g_cnt = 0;                   // complex elements of the batch's grid-1 region (starts at 0)
     bool sparse = false;                 // spread only the non-empty tiles after clearing the grid-1 region
-    int64_t list_off = 0, list_cnt = 0;  // the batch's non-empty tiles in the direction's tile list
+    int64_t list_off = 0, list_cnt = 0;  // the batch's spreading tiles in the direction's descriptor list
+                                         //   (sparse batches: the non-empty tiles; others: every tile)
     int64_t pre_ttiles = 0;              // offset of the batch's transpose-tile prefix array
     int64_t ws_end = 0;                  // end of the batch's workspace use (complex elements)
     int64_t pre_pts = 0, pre_tgts = 0;   // offsets into the prefix arrays (pre_tgts: interp workgroups)
@@ -129,7 +158,7 @@ struct DirPlan {                         // one direction (synthesis or analysis
     std::vector<int64_t> pre_stiles;     // per batch: npairs+1 prefix sums of spreading tiles
     std::vector<int64_t> pre_ttiles;     // per batch: npairs+1 prefix sums of transpose tiles
     int64_t tiles_total = 0;             // spreading tiles over all batches
-    std::vector<int64_t> tile_list;      // batch-local indices of non-empty tiles of sparse batches
+    std::vector<SpreadTile> spread_tiles;   // spreading tiles of every batch (built with the binning)
     std::vector<DirectItem> direct;
     double grid_cells = 0.0, direct_terms = 0.0;
     double est_seconds = 0.0;

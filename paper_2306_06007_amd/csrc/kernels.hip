@@ -42,8 +42,10 @@ template <typename T> __device__ __forceinline__ cplx<T> cmuli(cplx<T> a, T s) {
 // exponential of semicircle ES(z) = exp(beta (sqrt(1 - z^2) - 1)), |z| < 1
 __device__ __forceinline__ float es_kernel(float z, float beta)
 {
+    // hardware square root and base-2 exponential (about 1 ulp each): far
+    // below the kernel's own truncation error at any float32 tolerance
     float q = 1.0f - z * z;
-    return q > 0.0f ? __expf(beta * (sqrtf(q) - 1.0f)) : 0.0f;
+    return q > 0.0f ? __builtin_amdgcn_exp2f(beta * 1.44269504088896341f * (__builtin_amdgcn_sqrtf(q) - 1.0f)) : 0.0f;
 }
 __device__ __forceinline__ double es_kernel(double z, double beta)
 {
@@ -80,6 +82,8 @@ __device__ __forceinline__ int small_div(int a, float rd)
     return static_cast<int>((static_cast<float>(a) + 0.5f) * rd);
 }
 static_assert(kFftElems < (1 << 21), "FFT workgroup indices must stay below 2^21 for small_div");
+static_assert(int64_t(kFftMaxLen / kTileX) * (kFftMaxLen / kTileY) * (kFftMaxLen / kTileZ) < (int64_t(1) << 31),
+              "grid-1 tiles of a sub-problem must fit 31 bits");
 
 // ---------------------------------------------------------------------------
 // fills
@@ -135,7 +139,8 @@ __device__ __forceinline__ void source_footprint(const PairDev &P, const double 
 
 // Plan-time binning: every (sub-problem, source) pair is listed under each
 // grid-1 tile its w^3 footprint touches.  Pass 1 (cursor == nullptr)
-// counts, pass 2 scatters source indices to the offsets the host computed.
+// counts, pass 2 scatters the pair's index in the batch's staging order to
+// the offsets the host computed.
 __global__ void k_bin_points(const PairDev *__restrict__ pairs, const int64_t *__restrict__ prefix, int npairs,
                              int64_t total, const double *__restrict__ xyz, int64_t nsrc, int w,
                              int32_t *__restrict__ counts, unsigned long long *__restrict__ cursor,
@@ -165,7 +170,7 @@ __global__ void k_bin_points(const PairDev *__restrict__ pairs, const int64_t *_
                     atomicAdd(counts + tile, 1);
                 } else {
                     const unsigned long long pos = atomicAdd(cursor + tile, 1ull);
-                    records[pos] = (int32_t)n;
+                    records[pos] = (int32_t)g;   // batches hold fewer than 2^31 sources
                 }
             }
 }
@@ -173,102 +178,131 @@ __global__ void k_bin_points(const PairDev *__restrict__ pairs, const int64_t *_
 // Gather + pre-phase of a batch's sources (type-3 centring, the source side):
 // c'_n = c_perm(n) exp(2 pi i iota s_c.(x_n - x_c)) for every source of every
 // sub-problem of the batch, in the batch's order (sub-problem, then chunk
-// order).  The phase is float64.
+// order), staged with its kernel footprint on grid 1 for the spreading pass
+// (computed once per source instead of once per tile it touches).  The phase
+// and the footprint are float64.
 template <typename T>
 __global__ void k_prephase(const PairDev *__restrict__ pairs, const int64_t *__restrict__ pprefix, int npairs,
                            int64_t total, const double *__restrict__ xyz, int64_t nsrc,
                            const int32_t *__restrict__ perm, const cplx<T> *__restrict__ in,
-                           cplx<T> *__restrict__ stage, double iota)
+                           StagedSrc<T> *__restrict__ stage, double iota, int w)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total) return;
     const int p = (int)find_segment(pprefix, npairs, g);
     const PairDev &P = pairs[p];
     const int64_t n = P.src_off + (g - pprefix[p]);
+    double xp[3], t[3];
+    int c0[3];
+    source_footprint(P, xyz, nsrc, n, w, xp, t, c0);
     double ph = 0.0;
-    for (int d = 0; d < 3; ++d) ph += P.sc[d] * (xyz[d * nsrc + n] - P.xc[d]);
+    for (int d = 0; d < 3; ++d) ph += P.sc[d] * xp[d];
     const double2 e = cis_cycles(ph, iota);
     const cplx<T> c = in[perm[n]];
-    stage[g] = mk<T>(T(c.x * e.x - c.y * e.y), T(c.x * e.y + c.y * e.x));
+    StagedSrc<T> s;
+    s.v[0] = T(c.x * e.x - c.y * e.y);
+    s.v[1] = T(c.x * e.y + c.y * e.x);
+    for (int d = 0; d < 3; ++d) {
+        s.frac[d] = T((double)(c0[d] - P.n1[d] / 2) - t[d]);
+        s.c0[d] = c0[d];
+    }
+    stage[g] = s;
 }
 
-// One workgroup per grid-1 tile.  Thread (x, y) of the 32 x 8 face owns the
-// kTileZ cells of its column; the tile's sources are staged kSpreadBatch at a
-// time (their pre-phased values, footprint origin and 3w kernel values in
-// LDS), every thread adds the contributions that fall in its cells, and the
-// whole tile is written once (no atomics; for a given plan the result is
-// deterministic).  The tile's sub-problem comes from a plan-time table, its
-// source list from the plan-time binning, the values from the pre-phase pass.
-template <typename T>
-__global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pairs, const int32_t *__restrict__ tile_pair,
-                                                int64_t tile_base, const int64_t *__restrict__ pprefix,
-                                                const int64_t *__restrict__ tile_list,
-                                                const int64_t *__restrict__ toff,
-                                                const int32_t *__restrict__ records, const double *__restrict__ xyz,
-                                                int64_t nsrc, const cplx<T> *__restrict__ stage,
-                                                cplx<T> *__restrict__ ws, int w, T beta)
+// eight consecutive LDS values (16-byte aligned) as wide reads
+__device__ __forceinline__ void load8(const float *p, float v[8])
 {
-    __shared__ T ker[kSpreadBatch][3 * kWMax];
+    const float4 a = reinterpret_cast<const float4 *>(p)[0], b = reinterpret_cast<const float4 *>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+__device__ __forceinline__ void load8(const double *p, double v[8])
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double2 a = reinterpret_cast<const double2 *>(p)[i];
+        v[2 * i] = a.x;
+        v[2 * i + 1] = a.y;
+    }
+}
+
+// Spreading by grid-1 tile: one workgroup per tile.  Thread (x, y) of the
+// 32 x 8 face owns the kTileZ cells of its column (a wavefront per 8 x 8 patch
+// of the face); the tile's sources are staged kSpreadBatch at a time in LDS
+// (pre-phased value, footprint origin relative to the tile, the 2w x and y
+// kernel values in the source's frame and the kTileZ z values in the tile's
+// frame, zero outside the footprint), every thread adds the contributions that
+// fall in its column with two wide LDS reads and 2 kTileZ FMAs per source, and
+// the whole tile is written once (no atomics; for a given plan the result is
+// deterministic).  The tile's sub-problem, corner and source list come from
+// one plan-time descriptor (the binning), each source's value and footprint
+// from the pre-phase pass.
+template <typename T>
+__global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pairs,
+                                                const SpreadTile *__restrict__ tiles,
+                                                const int32_t *__restrict__ records,
+                                                const StagedSrc<T> *__restrict__ staged, cplx<T> *__restrict__ ws,
+                                                int w, T beta, T two_over_w, float rwk)
+{
+    static_assert(kTileZ == 8, "the z weights of a source are read as 8 values");
+    // per staged source: kTileZ z values in the tile's frame, then w x and w y
+    // values in the source's frame (rows a multiple of 16 bytes)
+    constexpr int kKv = kTileZ + 2 * kWMax;
+    static_assert(kKv % 4 == 0, "16-byte rows");
+    __shared__ __align__(16) T kv[kSpreadBatch][kKv];
     __shared__ T frac[kSpreadBatch][3];
     __shared__ cplx<T> val[kSpreadBatch];
     __shared__ int org[kSpreadBatch][3];
     const int tid = threadIdx.x;
-    const int64_t gt = tile_base + (tile_list ? tile_list[blockIdx.x] : (int64_t)blockIdx.x);
-    const int p = tile_pair[gt];
-    const int64_t r0 = toff[gt], r1 = toff[gt + 1];
-    const PairDev &P = pairs[p];
-    const int64_t lt = gt - P.tile0;
-    const int tx = (int)(lt % P.ntile[0]);
-    const int ty = (int)((lt / P.ntile[0]) % P.ntile[1]);
-    const int tz = (int)(lt / ((int64_t)P.ntile[0] * P.ntile[1]));
-    const int ox = tx * kTileX, oy = ty * kTileY, oz = tz * kTileZ;
-    const int x = tid % kTileX, y = tid / kTileX;
-    const T two_over_w = T(2) / T(w);
-    const int w3 = 3 * w;
-    const float rw = 1.0f / static_cast<float>(w), rw3 = 1.0f / static_cast<float>(w3);
-    const cplx<T> *sv = stage + pprefix[p] - P.src_off;   // staged value of source n: sv[n]
+    const SpreadTile tile = tiles[blockIdx.x];
+    const int ox = tile.org[0], oy = tile.org[1], oz = tile.org[2];
+    // each wavefront owns an 8 x 8 patch of columns (x fastest): a w-wide
+    // footprint meets one or two of the four wavefronts instead of all of them
+    static_assert(kTileX == 32 && kTileY == 8, "8 x 8 column patches per wavefront");
+    const int x = (tid & 7) + 8 * (tid >> 6), y = (tid >> 3) & 7;
+    const int wk = 2 * w + kTileZ;   // kernel values per staged source
     T accr[kTileZ], acci[kTileZ];
 #pragma unroll
     for (int z = 0; z < kTileZ; ++z) accr[z] = acci[z] = T(0);
 
-    for (int64_t base = r0; base < r1; base += kSpreadBatch) {
-        const int cnt = (int)min((int64_t)kSpreadBatch, r1 - base);
+    for (int base = 0; base < tile.cnt; base += kSpreadBatch) {
+        const int cnt = min(kSpreadBatch, tile.cnt - base);
         __syncthreads();
         if (tid < cnt) {
-            const int64_t n = records[base + tid];
-            double xp[3], t[3];
-            int c0[3];
-            source_footprint(P, xyz, nsrc, n, w, xp, t, c0);
-            for (int d = 0; d < 3; ++d) frac[tid][d] = T((double)(c0[d] - P.n1[d] / 2) - t[d]);
-            org[tid][0] = c0[0] - ox;
-            org[tid][1] = c0[1] - oy;
-            org[tid][2] = c0[2] - oz;
-            val[tid] = sv[n];
+            const StagedSrc<T> sc = staged[records[tile.r0 + base + tid]];
+            for (int d = 0; d < 3; ++d) frac[tid][d] = sc.frac[d];
+            org[tid][0] = sc.c0[0] - ox;
+            org[tid][1] = sc.c0[1] - oy;
+            org[tid][2] = sc.c0[2] - oz;
+            val[tid] = mk<T>(sc.v[0], sc.v[1]);
         }
         __syncthreads();
-        for (int i = tid; i < cnt * w3; i += 256) {
-            const int j = small_div(i, rw3), r = i - __mul24(j, w3);
-            const int d = small_div(r, rw), q = r - __mul24(d, w);
-            ker[j][r] = es_kernel((frac[j][d] + T(q)) * two_over_w, beta);
+        // one branch-free evaluation per entry: z entries take their offset
+        // from the tile, x and y entries from the footprint origin
+        for (int i = tid; i < cnt * wk; i += 256) {
+            const int j = small_div(i, rwk), r = i - __mul24(j, wk);
+            const int rr = r - kTileZ;
+            const int d = r < kTileZ ? 2 : (rr >= w ? 1 : 0);
+            const int q = r < kTileZ ? r - (&org[0][0])[__mul24(j, 3) + 2] : rr - (d ? w : 0);
+            const T k = es_kernel(((&frac[0][0])[__mul24(j, 3) + d] + T(q)) * two_over_w, beta);
+            (&kv[0][0])[__mul24(j, kKv) + r] = (unsigned)q < (unsigned)w ? k : T(0);
         }
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
             const int qx = x - org[j][0], qy = y - org[j][1];
             if ((unsigned)qx >= (unsigned)w || (unsigned)qy >= (unsigned)w) continue;
-            const T kxy = ker[j][qx] * ker[j][w + qy];
+            const T kxy = kv[j][kTileZ + qx] * kv[j][kTileZ + w + qy];
             const T vr = val[j].x * kxy, vi = val[j].y * kxy;
-            const int oz0 = org[j][2];
+            T kz[kTileZ];
+            load8(kv[j], kz);
 #pragma unroll
             for (int z = 0; z < kTileZ; ++z) {
-                const int qz = z - oz0;
-                if ((unsigned)qz < (unsigned)w) {
-                    const T kz = ker[j][2 * w + qz];
-                    accr[z] += vr * kz;
-                    acci[z] += vi * kz;
-                }
+                accr[z] += vr * kz[z];
+                acci[z] += vi * kz[z];
             }
         }
     }
+    const PairDev &P = pairs[tile.pair];
     const int gx = ox + x, gy = oy + y;
     if (gx < P.n1[0] && gy < P.n1[1]) {
         cplx<T> *grid = ws + P.bufG;
@@ -863,25 +897,24 @@ hipError_t launch_bin(const PairDev *pairs, const int64_t *prefix, int npairs, i
 
 template <typename T>
 hipError_t launch_prephase(const PairDev *pairs, const int64_t *pprefix, int npairs, int64_t total, const double *xyz,
-                           int64_t nsrc, const int32_t *perm, const void *in, void *stage, double iota, hipStream_t st)
+                           int64_t nsrc, const int32_t *perm, const void *in, void *stage, double iota, int w,
+                           hipStream_t st)
 {
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_prephase<T>, dim3(blocks_for(total, 256, INT32_MAX)), dim3(256), 0, st, pairs, pprefix,
-                       npairs, total, xyz, nsrc, perm, static_cast<const cplx<T> *>(in), static_cast<cplx<T> *>(stage),
-                       iota);
+                       npairs, total, xyz, nsrc, perm, static_cast<const cplx<T> *>(in),
+                       static_cast<StagedSrc<T> *>(stage), iota, w);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_spread(const PairDev *pairs, const int32_t *tile_pair, int64_t tile_base, const int64_t *pprefix,
-                         int64_t tiles, const int64_t *tile_list, const int64_t *toff, const int32_t *records,
-                         const double *xyz, int64_t nsrc, const void *stage, void *ws, int w, double beta,
-                         hipStream_t st)
+hipError_t launch_spread(const PairDev *pairs, const SpreadTile *tiles, int64_t ntiles, const int32_t *records,
+                         const void *stage, void *ws, int w, double beta, hipStream_t st)
 {
-    if (tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spread<T>, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, st, pairs, tile_pair, tile_base,
-                       pprefix, tile_list, toff, records, xyz, nsrc, static_cast<const cplx<T> *>(stage),
-                       static_cast<cplx<T> *>(ws), w, T(beta));
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spread<T>, dim3(static_cast<unsigned>(ntiles)), dim3(256), 0, st, pairs, tiles, records,
+                       static_cast<const StagedSrc<T> *>(stage), static_cast<cplx<T> *>(ws), w, T(beta), T(2.0 / w),
+                       1.0f / static_cast<float>(2 * w + kTileZ));
     return hipGetLastError();
 }
 
@@ -978,15 +1011,13 @@ hipError_t launch_finalize(const double *acc, int64_t n, const int32_t *perm, vo
 }
 
 template hipError_t launch_prephase<float>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
-                                           const int32_t *, const void *, void *, double, hipStream_t);
+                                           const int32_t *, const void *, void *, double, int, hipStream_t);
 template hipError_t launch_prephase<double>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
-                                            const int32_t *, const void *, void *, double, hipStream_t);
-template hipError_t launch_spread<float>(const PairDev *, const int32_t *, int64_t, const int64_t *, int64_t,
-                                         const int64_t *, const int64_t *, const int32_t *, const double *, int64_t,
+                                           const int32_t *, const void *, void *, double, int, hipStream_t);
+template hipError_t launch_spread<float>(const PairDev *, const SpreadTile *, int64_t, const int32_t *,
                                          const void *, void *, int, double, hipStream_t);
-template hipError_t launch_spread<double>(const PairDev *, const int32_t *, int64_t, const int64_t *, int64_t,
-                                          const int64_t *, const int64_t *, const int32_t *, const double *, int64_t,
-                                          const void *, void *, int, double, hipStream_t);
+template hipError_t launch_spread<double>(const PairDev *, const SpreadTile *, int64_t, const int32_t *,
+                                         const void *, void *, int, double, hipStream_t);
 template hipError_t launch_fft<float>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,
                                       const void *, int, int, double, hipStream_t);
 template hipError_t launch_fft<double>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,

@@ -576,7 +576,7 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
     dp->pre_tgts.clear();
     dp->pre_stiles.clear();
     dp->pre_ttiles.clear();
-    dp->tile_list.clear();
+    dp->spread_tiles.clear();
     dp->tiles_total = 0;
     for (int q = 0; q < 3; ++q) dp->pre_tiles[q].clear();
     const int64_t cap = static_cast<int64_t>(hp.ws_elems);
@@ -584,11 +584,13 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
     while (k < nufft.size()) {
         Batch b;
         b.pair0 = static_cast<int64_t>(dp->pairs.size());
-        int64_t sumG = 0, sumA = 0, sumB = 0;
+        int64_t sumG = 0, sumA = 0, sumB = 0, npts = 0;
         size_t k1 = k;
         while (k1 < nufft.size()) {
             const int64_t gg = nufft[k1].g.g1, a = nufft[k1].g.bufA, bb = nufft[k1].g.bufB;
-            if (k1 > k && sumG + sumA + sumB + gg + a + bb > cap) break;
+            const int64_t np = src.off[nufft[k1].i + 1] - src.off[nufft[k1].i];
+            if (k1 > k && (sumG + sumA + sumB + gg + a + bb > cap || npts + np > kMaxBatchPts)) break;
+            npts += np;
             sumG += gg;
             sumA += a;
             sumB += bb;
@@ -674,12 +676,11 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
             dp->pre_tgts.push_back(dp->pre_tgts.back() + iblk);
             dp->grid_cells += static_cast<double>(g.g1);
             // algorithmic HBM bytes per kernel (see the kernel documentation)
-            // spreading writes every grid-1 cell once and reads each source
-            // (coordinates, permutation, value, tile record) per tile it touches
-            // gather + pre-phase: coordinates, permutation, input value, staged value per source
-            dp->alg_bytes[HVOX_K_PREPHASE] += pd.src_cnt * (24.0 + 4.0 + 2.0 * delta);
-            // spreading: tile record, coordinates and staged value per source, grid 1 written once
-            dp->alg_bytes[HVOX_K_SPREAD] += pd.src_cnt * (4.0 + 24.0 + delta) + delta * static_cast<double>(g.g1);
+            // gather + pre-phase: coordinates, permutation, input value read, staged source written
+            const double staged = p.dtype == HVOX_F64 ? sizeof(StagedSrc<double>) : sizeof(StagedSrc<float>);
+            dp->alg_bytes[HVOX_K_PREPHASE] += pd.src_cnt * (24.0 + 4.0 + delta + staged);
+            // spreading: tile record and staged source per source, grid 1 written once
+            dp->alg_bytes[HVOX_K_SPREAD] += pd.src_cnt * (4.0 + staged) + delta * static_cast<double>(g.g1);
             dp->alg_bytes[HVOX_K_FFT_X] += delta * (static_cast<double>(g.g1) + g.bx);
             dp->alg_bytes[HVOX_K_TRANSPOSE] += delta * 2.0 * static_cast<double>(g.bx);
             dp->alg_bytes[HVOX_K_FFT_Y] += delta * (static_cast<double>(g.bx) + g.cy);
