@@ -349,15 +349,18 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
     if (e != hipSuccess) return bad(e, "binning count pass");
     std::vector<int64_t> off(nt + 1, 0);
     for (int64_t i = 0; i < nt; ++i) off[i + 1] = off[i] + counts[i];
-    // batches whose grid 1 is mostly empty: clear it with one fill, spread only
-    // the non-empty tiles; other batches spread every tile (empty ones write zeros)
+    // batches whose grid 1 is mostly empty (under a third of the tiles hold
+    // sources): clear it with one fill, spread only the non-empty tiles; other
+    // batches spread every tile (empty ones write zeros), which writes each cell
+    // once instead of twice (the fill streams at ~6.5 TB/s, an empty tile of the
+    // spreading kernel at ~4.5 TB/s, so the fill pays only below about a third)
     dp.spread_tiles.clear();
     const double delta = pl->hp.prm.dtype == HVOX_F64 ? 16.0 : 8.0;
     for (Batch &b : dp.batches) {
         const int64_t t0 = dp.pairs[b.pair0].tile0;
         int64_t nonempty = 0;
         for (int64_t t = 0; t < b.stiles; ++t) nonempty += counts[t0 + t] > 0;
-        b.sparse = 2 * nonempty < b.stiles;
+        b.sparse = 3 * nonempty < b.stiles;
         b.list_off = static_cast<int64_t>(dp.spread_tiles.size());
         double listed_cells = 0.0;
         for (int64_t i = 0; i < b.npairs; ++i) {
