@@ -359,8 +359,13 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
     for (Batch &b : dp.batches) {
         const int64_t t0 = dp.pairs[b.pair0].tile0;
         int64_t nonempty = 0;
-        for (int64_t t = 0; t < b.stiles; ++t) nonempty += counts[t0 + t] > 0;
-        b.sparse = 3 * nonempty < b.stiles;
+        bool crowded = false;
+        for (int64_t t = 0; t < b.stiles; ++t) {
+            nonempty += counts[t0 + t] > 0;
+            crowded = crowded || counts[t0 + t] > kSpreadSplit;
+        }
+        // a batch with crowded tiles (split into atomically adding parts) needs the fill too
+        b.sparse = crowded || 3 * nonempty < b.stiles;
         b.list_off = static_cast<int64_t>(dp.spread_tiles.size());
         double listed_cells = 0.0;
         for (int64_t i = 0; i < b.npairs; ++i) {
@@ -371,13 +376,19 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
                     for (int32_t tx = 0; tx < pd.ntile[0]; ++tx, ++gt) {
                         if (b.sparse && counts[gt] == 0) continue;
                         SpreadTile d{};
-                        d.r0 = off[gt];
-                        d.cnt = counts[gt];
                         d.pair = static_cast<int32_t>(i);
                         d.org[0] = static_cast<int16_t>(tx * kTileX);
                         d.org[1] = static_cast<int16_t>(ty * kTileY);
                         d.org[2] = static_cast<int16_t>(tz * kTileZ);
-                        dp.spread_tiles.push_back(d);
+                        d.flags = counts[gt] > kSpreadSplit ? kSpreadAdd : 0;
+                        int32_t done = 0;
+                        do {   // a crowded tile: parts of at most kSpreadSplit sources
+                            d.r0 = off[gt] + done;
+                            d.cnt = std::min(counts[gt] - done, kSpreadSplit);
+                            if (!(d.flags & kSpreadAdd)) d.cnt = counts[gt];
+                            dp.spread_tiles.push_back(d);
+                            done += d.cnt;
+                        } while (done < counts[gt]);
                         listed_cells += static_cast<double>(std::min(kTileX, pd.n1[0] - tx * kTileX)) *
                                         std::min(kTileY, pd.n1[1] - ty * kTileY) *
                                         std::min(kTileZ, pd.n1[2] - tz * kTileZ);

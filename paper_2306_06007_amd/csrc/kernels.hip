@@ -234,7 +234,10 @@ __device__ __forceinline__ void load8(const double *p, double v[8])
 // frame, zero outside the footprint), every thread adds the contributions that
 // fall in its column with two wide LDS reads and 2 kTileZ FMAs per source, and
 // the whole tile is written once (no atomics; for a given plan the result is
-// deterministic).  The tile's sub-problem, corner and source list come from
+// deterministic).  A crowded tile (more than kSpreadSplit sources) is split
+// into parts, one workgroup each, that add their sums atomically into the
+// zero-filled grid (float atomics: the rounding order of those cells varies
+// from run to run).  The tile's sub-problem, corner and source list come from
 // one plan-time descriptor (the binning), each source's value and footprint
 // from the pre-phase pass.
 template <typename T>
@@ -306,10 +309,22 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
     const int gx = ox + x, gy = oy + y;
     if (gx < P.n1[0] && gy < P.n1[1]) {
         cplx<T> *grid = ws + P.bufG;
+        if (tile.flags & kSpreadAdd) {
 #pragma unroll
-        for (int z = 0; z < kTileZ; ++z) {
-            const int gz = oz + z;
-            if (gz < P.n1[2]) grid[((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx] = mk<T>(accr[z], acci[z]);
+            for (int z = 0; z < kTileZ; ++z) {
+                const int gz = oz + z;
+                if (gz < P.n1[2]) {
+                    T *c = reinterpret_cast<T *>(grid + ((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx);
+                    atomicAdd(c, accr[z]);
+                    atomicAdd(c + 1, acci[z]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int z = 0; z < kTileZ; ++z) {
+                const int gz = oz + z;
+                if (gz < P.n1[2]) grid[((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx] = mk<T>(accr[z], acci[z]);
+            }
         }
     }
 }

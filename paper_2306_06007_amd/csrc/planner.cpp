@@ -27,10 +27,14 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 
 // Cost-model rates used to choose NUFFT or direct summation for each
-// sub-problem, calibrated against MI355X kernel timings of the 995k x 1M
-// SKA-like workload: the NUFFT kernels (spread, FFT passes, transpose,
-// interpolation) together sustained ~1.5e12 algorithmic bytes/s; the direct
-// kernel 2.7e12 (float32) and 8e11 (float64) terms/s.
+// sub-problem, from MI355X kernel timings: the grid passes (FFT passes,
+// transpose, fills) sustain ~3e12 algorithmic bytes/s of the byte model
+// below and the spreading / interpolation kernels ~4e11 kernel-cell updates/s
+// in float32 and ~8e11 in float64 (its 14-wide footprints fill more lanes of
+// a wavefront, and float64 FMAs issue at the float32 rate); the direct
+// kernel 3.0e12 (float32) and 9.2e11 (float64) terms/s.  A sweep of the
+// decision threshold on the SKA-like and dense DCOS workloads puts the
+// fastest split at these rates (threshold 1).
 struct Rates {
     double hbm_bytes_per_s;     // effective streaming rate of the grid passes
     double cells_per_s;         // spread/interp kernel-cell updates
@@ -40,8 +44,8 @@ struct Rates {
 
 Rates rates_for(int dtype)
 {
-    if (dtype == HVOX_F64) return {1.5e12, 1.0e11, 8.0e11, 4e-6};
-    return {1.5e12, 2.0e11, 2.7e12, 4e-6};
+    if (dtype == HVOX_F64) return {3.0e12, 8.0e11, 9.2e11, 4e-6};
+    return {3.0e12, 4.0e11, 3.0e12, 4e-6};
 }
 
 }  // namespace

@@ -234,6 +234,37 @@ def lofar_like(seed: int = 3, n_pix: int = 4_000_000, cap_deg: float = 60.0,
                     dict(seed=seed, cap_deg=cap_deg))
 
 
+# Telescope-radius ladder of the paper's runtime experiments (Sect. 5.1 and
+# its table of telescope scales): radius in km -> (visibility count, pixels
+# per side of the dense DCOS image).  The image side reproduces the table's
+# pixel counts exactly (80^2 = 6,400 ... 13,500^2 = 182.25M).
+DENSE_LADDER = {0.1: (273, 80), 0.3: (13_000, 160), 1.0: (95_000, 360), 3.0: (148_000, 900),
+                10.0: (238_000, 3200), 30.0: (341_000, 8640), 100.0: (394_000, 13_500)}
+
+
+def dense_dcos(radius_km: float = 3.0, seed: int = 5, ntrans: int = 1, fov_deg: float = 30.0,
+               lat_deg: float = -26.82, dec_deg: float = -45.0, wavelength_m: float = 2.0) -> Workload:
+    """Dense-mesh case shaped after the paper's runtime ladder (default
+    parameters of its benchmarks: an SKA-Low-like array at 150 MHz, one
+    channel, three equi-spaced time intervals over 8 hours, declination -45 deg,
+    a 30-degree DCOS image).  The SKA-Low station table is not available: the
+    stations sit at log-radial distances between 15 m and the telescope radius
+    (a dense core, sparse outskirts), their count chosen so that three
+    snapshots give the ladder's visibility count.  The image is the ladder's
+    square DCOS grid around the phase centre; intensities U[0,1]."""
+    n_vis_target, n_side = DENSE_LADDER[float(radius_km)]
+    rng = np.random.default_rng(seed)
+    n_st = max(2, int(round(0.5 + math.sqrt(0.25 + 2.0 * n_vis_target / 3.0))))
+    enu = log_radial_layout(n_st, 15.0, radius_km * 1e3, rng)
+    H = np.radians(np.linspace(-60.0, 60.0, 3))          # -4 h, 0, +4 h
+    uvw = earth_rotation_uvw(enu, lat_deg, dec_deg, H, [wavelength_m])
+    xyz = dcos_grid(n_side, fov_deg)
+    sky = real_intensities(ntrans, xyz.shape[0], rng)
+    vis = complex_normal(ntrans, uvw.shape[0], rng)
+    return Workload(f"dense-dcos-{radius_km:g}km-{uvw.shape[0]}-vis-{xyz.shape[0]}-pix", uvw, xyz, sky, vis,
+                    dict(seed=seed, radius_km=radius_km, n_stations=n_st, n_side=n_side, fov_deg=fov_deg))
+
+
 @dataclass
 class Request:
     rid: int

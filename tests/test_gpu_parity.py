@@ -265,3 +265,29 @@ def test_lofar_like_full_size_sampled(lofar_like, dtype, eps):
     _report(f"lofar-like full {dtype} {eps:g}", es, ea, info)
     assert info["n_vis_chunks"] > 1 and info["n_sky_chunks"] > 1   # chunked evaluation
     assert es <= eps and ea <= eps
+
+
+# ---- dense DCOS meshes of the paper's telescope-radius ladder, sampled rows -------------
+# (the regime where most of the terms go through NUFFT sub-problems)
+@pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
+@pytest.mark.parametrize("radius_km", [3.0, pytest.param(10.0, marks=pytest.mark.slow)])
+def test_dense_dcos_ladder_sampled(radius_km, dtype, eps):
+    wl = W.dense_dcos(radius_km)
+    rv = W.sample_rows(wl.n_vis, 256, seed=41)
+    rp = W.sample_rows(wl.n_pix, 256, seed=42)
+    es, ea, info = both_directions(wl.uvw, wl.xyz, wl.sky, wl.vis, eps, dtype, rows_vis=rv, rows_pix=rp)
+    _report(f"dense {radius_km:g} km {dtype} {eps:g}", es, ea, info)
+    assert info["n_pairs_nufft"] > 0          # NUFFT sub-problems take part
+    assert es <= eps and ea <= eps
+
+
+def test_dense_dcos_forced_nufft_sampled():
+    """Every sub-problem of the 1 km rung as a NUFFT (float32, eps 1e-4)."""
+    wl = W.dense_dcos(1.0)
+    rv = W.sample_rows(wl.n_vis, 256, seed=43)
+    rp = W.sample_rows(wl.n_pix, 256, seed=44)
+    es, ea, info = both_directions(wl.uvw, wl.xyz, wl.sky, wl.vis, 1e-4, "f32", rows_vis=rv, rows_pix=rp,
+                                   direct_threshold=0.0)
+    _report("dense 1 km forced nufft f32", es, ea, info)
+    assert info["n_pairs_direct"] == 0
+    assert es <= 1e-4 and ea <= 1e-4

@@ -191,3 +191,20 @@ def test_plan_without_gpu_raises_cleanly():
     wl = W.compact_disk(n_vis=10, n_pix=10)
     with pytest.raises(RuntimeError):
         hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32")
+
+
+@pytest.mark.parametrize("radius_km", [0.1, 1.0, 3.0])
+def test_dense_ladder_shapes_and_host_plan(radius_km):
+    """The dense DCOS ladder reproduces the paper's pixel counts exactly and
+    its visibility counts within 1%; its host plan covers every (vis, pix)
+    term once, through NUFFT grids or direct blocks."""
+    wl = W.dense_dcos(radius_km)
+    n_vis, n_side = W.DENSE_LADDER[radius_km]
+    assert wl.n_pix == n_side * n_side
+    assert abs(wl.n_vis - n_vis) <= 0.01 * n_vis + 3
+    assert np.allclose(np.linalg.norm(wl.xyz, axis=1), 1.0)
+    assert np.abs(wl.uvw[:, :2]).max() <= 2 * radius_km * 1e3 / 2.0 + 1e-6   # baselines <= 2R, 2 m wavelength
+    with hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True) as p:
+        info = p.info()
+    assert info["n_pairs_nufft"] + info["n_pairs_direct"] == info["n_vis_chunks"] * info["n_sky_chunks"]
+    assert info["direct_terms"] <= float(wl.n_vis) * wl.n_pix
