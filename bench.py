@@ -254,7 +254,7 @@ def main():
     def _run_mode(wl, dtype, eps, direct_threshold, steps, warm, ntrans):
         cd = torch.complex64 if dtype == "f32" else torch.complex128
         t0 = time.perf_counter()
-        plan = hv.Plan(wl.uvw, wl.xyz, eps, dtype, direct_threshold=direct_threshold)
+        plan = hv.Plan(wl.uvw, wl.xyz, eps, dtype, direct_threshold=direct_threshold, ntrans_hint=ntrans)
         plan_s = time.perf_counter() - t0
         sky, vis = wl.sky, wl.vis
         if ntrans > 1:   # further rows: the same data rotated, so every row differs

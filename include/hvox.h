@@ -90,7 +90,10 @@ typedef struct {
                                  Algorithm 2 on the visibility domain (Sect. 4, allocate()). */
     const int32_t *sky_chunk; /* same for the sky domain ([n_pix]). */
     int32_t flags;            /* HVOX_REAL_SKY | HVOX_PLAN_HOST_ONLY | HVOX_TIMING */
-    int32_t reserved;
+    int32_t ntrans_hint;      /* data rows per call the NUFFT/direct choice is weighed for; 0 -> 1,
+                                 negative -> HVOX_ERR_ARG.  The direct sum shares its phase factors
+                                 among up to four rows while a NUFFT sub-problem repeats per row, so
+                                 batched calls favour direct blocks.  Results never depend on it. */
 } hvox_opts;
 
 /* What a plan decided.  Sizes in bytes; counts of sub-problems are per
@@ -116,7 +119,7 @@ typedef struct {
     int64_t max_pair_workspace_bytes;
     double  grid_cells;       /* sum over NUFFT sub-problems of the grid-1 cell counts */
     double  direct_terms;     /* sum over direct sub-problems of N_src * N_tgt */
-    double  est_seconds;      /* cost-model estimate of one synthesis + one analysis */
+    double  est_seconds;      /* cost-model estimate of one synthesis + one analysis (of ntrans_hint rows) */
     double  plan_seconds;     /* host + device time spent in hvox_plan */
 } hvox_plan_info_t;
 

@@ -633,6 +633,8 @@ int hvox_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t n_pix
     prm.direct_threshold = o.direct_threshold;
     if (std::isnan(prm.direct_threshold)) return fail(HVOX_ERR_ARG, "direct_threshold is NaN");
     prm.flags = o.flags;
+    if (o.ntrans_hint < 0) return fail(HVOX_ERR_ARG, "ntrans_hint must be >= 0");
+    prm.ntrans_hint = o.ntrans_hint == 0 ? 1 : o.ntrans_hint;
     prm.all_direct = eps == 0.0 || std::isinf(prm.direct_threshold);
     if (eps > 0.0) {
         const double floor_eps = dtype == HVOX_F64 ? 1e-10 : 1e-5;

@@ -185,6 +185,7 @@ struct Params {
     double beta2 = 0.0;
     bool all_direct = false;
     double direct_threshold = -1.0;
+    int ntrans_hint = 1;           // rows per call the cost model weighs
     double max_fft_bytes = 500e6;
     double alpha = 1.0;
     double ws_cap = 4.0 * 1024 * 1024 * 1024;

@@ -44,7 +44,7 @@ class HvoxOpts(ctypes.Structure):
                 ("vis_chunk", ctypes.POINTER(ctypes.c_int32)),
                 ("sky_chunk", ctypes.POINTER(ctypes.c_int32)),
                 ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("ntrans_hint", ctypes.c_int32)]
 
 
 class HvoxPlanInfo(ctypes.Structure):
@@ -196,7 +196,7 @@ class Plan:
                  anisotropy: float = 0.0, upsampfac: float = 0.0, inner_upsampfac: float = 0.0,
                  direct_threshold: float = -1.0,
                  workspace_bytes: float = 0.0, vis_chunk=None, sky_chunk=None, real_sky: bool = False,
-                 host_only: bool = False, timing: bool = False, stream=None):
+                 host_only: bool = False, timing: bool = False, ntrans_hint: int = 1, stream=None):
         self._lib = load_library()
         self._plan = ctypes.c_void_p(None)
         uvw = _coords(uvw, "uvw")
@@ -213,6 +213,7 @@ class Plan:
         opts.inner_upsampfac = inner_upsampfac
         opts.direct_threshold = direct_threshold
         opts.workspace_bytes = workspace_bytes
+        opts.ntrans_hint = int(ntrans_hint)
         keep = []
         if vis_chunk is not None:
             vc = np.ascontiguousarray(vis_chunk, dtype=np.int32)

@@ -208,3 +208,19 @@ def test_dense_ladder_shapes_and_host_plan(radius_km):
         info = p.info()
     assert info["n_pairs_nufft"] + info["n_pairs_direct"] == info["n_vis_chunks"] * info["n_sky_chunks"]
     assert info["direct_terms"] <= float(wl.n_vis) * wl.n_pix
+
+
+def test_ntrans_hint_shifts_the_choice_towards_direct():
+    """The direct kernel shares its phase factors among up to four rows while a
+    NUFFT sub-problem repeats per row: a plan weighed for four rows keeps no
+    more NUFFT sub-problems than one weighed for one; a negative hint is an
+    argument error."""
+    wl = W.ska_like(n_pix=200000, n_ant=120, n_times=30)
+    with hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True) as p1, \
+            hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True, ntrans_hint=4) as p4:
+        i1, i4 = p1.info(), p4.info()
+    assert i4["n_pairs_nufft"] <= i1["n_pairs_nufft"]
+    assert i4["n_pairs_nufft"] + i4["n_pairs_direct"] == i1["n_pairs_nufft"] + i1["n_pairs_direct"]
+    assert i4["est_seconds"] > i1["est_seconds"]
+    with pytest.raises(hv.HvoxError):
+        hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True, ntrans_hint=-1)
