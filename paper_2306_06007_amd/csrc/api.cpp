@@ -847,7 +847,7 @@ extern "C" int hvox_test_fft(int32_t dtype, int32_t n, int32_t nin, int32_t nlin
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_one, dtype == HVOX_F64 ? static_cast<const void *>(ones.data()) : ones32.data(),
                            delta / 2 * ones.size(), hipMemcpyHostToDevice, st);
-    const int lds = pd.lines_per_tile[0] * n;
+    const int lds = fft_lds_elems(pd.lines_per_tile[0], n);
     if (e == hipSuccess)
         e = dtype == HVOX_F64
                 ? launch_fft<double>(static_cast<PairDev *>(d_pd), static_cast<int64_t *>(d_pre), 1, tiles, 0, d_ws,

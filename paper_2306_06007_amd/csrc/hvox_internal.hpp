@@ -27,6 +27,11 @@ constexpr int fft_lines(int n)
 {
     return n >= fft_elems(fft_threads(n)) ? 1 : (fft_elems(fft_threads(n)) / n < kFftMaxLines ? fft_elems(fft_threads(n)) / n : kFftMaxLines);
 }
+// lines of an FFT workgroup sit in LDS one element apart (line stride n + 1):
+// lines loaded across lanes (the z pass) and even lengths would otherwise map
+// every lane of an access to one or two banks
+constexpr int fft_lds_stride(int n) { return n + 1; }
+constexpr int fft_lds_elems(int lines, int n) { return lines * fft_lds_stride(n); }
 constexpr int kDirectThreads = 256;  // threads of a direct-sum workgroup
 constexpr int kDirectTile = 512;     // targets per direct-sum workgroup (two per thread)
 constexpr int kDirectSrcTile = 256;  // sources staged in LDS at a time

@@ -395,7 +395,7 @@ __device__ __forceinline__ void dft_small(cplx<T> *u, T s)
 // Butterfly i of a line: k = i mod p, inputs x[i + q n/R] twiddled by
 // w^(k q n / (p R)), outputs at (i - k) R + k + m p.
 template <typename T, int R, int NT>
-__device__ void fft_stage(cplx<T> *lds, int nl, int n, int p, const cplx<T> *tw, T s)
+__device__ void fft_stage(cplx<T> *lds, int nl, int n, int ls, int p, const cplx<T> *tw, T s)
 {
     constexpr int MAXB = (fft_elems(NT) / R + NT - 1) / NT;
     const int nbf = n / R;
@@ -412,7 +412,7 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int p, const cplx<T> *tw,
         if (b < total) {
             const int j = small_div(b, rnbf), i = b - __mul24(j, nbf);
             const int g = small_div(i, rp), k = i - __mul24(g, p);
-            const int lb = __mul24(j, n);
+            const int lb = __mul24(j, ls);   // line j starts at j * ls in LDS
             obase[c] = lb + __mul24(g, pR) + k;
             const int tk = __mul24(k, twstep);
 #pragma unroll
@@ -470,6 +470,7 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
     const int64_t line0 = tile * L;
     const int nl = (int)min((int64_t)L, lines - line0);
     const int half_in = nin / 2, half_n = n / 2;
+    const int ls = fft_lds_stride(n);   // LDS line stride
 
     {
         // twiddles of this line length, staged with the data (sign s applied here)
@@ -500,17 +501,19 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
         const T *px = precor + P.precor[0] + half_in;
         const float rn = 1.0f / static_cast<float>(n);
         T fx[EPT];             // x pre-correction (pass x), applied after all loads are issued
-        int jl[EPT];
+        int jl[EPT], slot[EPT];
 #pragma unroll
         for (int c = 0; c < EPT; ++c) {
             const int e = threadIdx.x + c * NT;
             v[c] = mk<T>(T(0), T(0));
             fx[c] = T(1);
             jl[c] = 0;
+            slot[c] = 0;
             if (e < ne) {
                 const int j = small_div(e, rn), f = e - __mul24(j, n);
                 const int l = f < half_n ? f : f - n;
                 jl[c] = j;
+                slot[c] = __mul24(j, ls) + f;
                 if (l >= -half_in && l < half_in) {
                     v[c] = sb[__mul24(j, nin) + l + half_in];
                     if (pass == 0) fx[c] = px[l];
@@ -520,7 +523,7 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
 #pragma unroll
         for (int c = 0; c < EPT; ++c) {
             const int e = threadIdx.x + c * NT;
-            if (e < ne) lds[e] = pass == 0 ? cscale<T>(v[c], fx[c] * lfac[jl[c]]) : v[c];
+            if (e < ne) lds[slot[c]] = pass == 0 ? cscale<T>(v[c], fx[c] * lfac[jl[c]]) : v[c];
         }
     } else {
         const cplx<T> *sb = src + line0;
@@ -534,7 +537,7 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
             if (e < ne) {
                 const int f = small_div(e, rl), j = e - __mul24(f, nl);
                 const int l = f < half_n ? f : f - n;
-                slot[c] = __mul24(j, n) + f;
+                slot[c] = __mul24(j, ls) + f;
                 if (l >= -half_in && l < half_in) v[c] = sb[(int64_t)(l + half_in) * lines + j];
             }
         }
@@ -546,11 +549,11 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
     int pc = 1;
     for (int st = 0; st < P.nrad[pass]; ++st) {
         const int R = P.radix[pass][st];
-        if (R == 8) fft_stage<T, 8, NT>(lds, nl, n, pc, ltw, s);
-        else if (R == 4) fft_stage<T, 4, NT>(lds, nl, n, pc, ltw, s);
-        else if (R == 2) fft_stage<T, 2, NT>(lds, nl, n, pc, ltw, s);
-        else if (R == 3) fft_stage<T, 3, NT>(lds, nl, n, pc, ltw, s);
-        else fft_stage<T, 5, NT>(lds, nl, n, pc, ltw, s);
+        if (R == 8) fft_stage<T, 8, NT>(lds, nl, n, ls, pc, ltw, s);
+        else if (R == 4) fft_stage<T, 4, NT>(lds, nl, n, ls, pc, ltw, s);
+        else if (R == 2) fft_stage<T, 2, NT>(lds, nl, n, ls, pc, ltw, s);
+        else if (R == 3) fft_stage<T, 3, NT>(lds, nl, n, ls, pc, ltw, s);
+        else fft_stage<T, 5, NT>(lds, nl, n, ls, pc, ltw, s);
         pc *= R;
     }
     // kept window: wstart is 0 (whole line) or -R with 2R < n, so wstart + q lies in (-n, n)
@@ -560,7 +563,7 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
         const int j = small_div(e, rw), q = e - __mul24(j, wcnt);
         int m = wst + q;
         if (m < 0) m += n;
-        out[e] = lds[__mul24(j, n) + m];
+        out[e] = lds[__mul24(j, ls) + m];
     }
 }
 

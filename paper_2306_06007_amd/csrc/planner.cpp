@@ -683,7 +683,7 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
                 int64_t tiles = (lines[q] + L - 1) / L;
                 b.tiles[q] += tiles;
                 dp->pre_tiles[q].push_back(dp->pre_tiles[q].back() + tiles);
-                b.lds_elems[q] = std::max<int32_t>(b.lds_elems[q], static_cast<int32_t>(L * g.n2[q]));
+                b.lds_elems[q] = std::max<int32_t>(b.lds_elems[q], fft_lds_elems(static_cast<int>(L), g.n2[q]));
                 b.max_pass_len[q] = std::max(b.max_pass_len[q], g.n2[q]);
             }
             b.pts += pd.src_cnt;
