@@ -82,6 +82,10 @@ __device__ __forceinline__ int small_div(int a, float rd)
     return static_cast<int>((static_cast<float>(a) + 0.5f) * rd);
 }
 static_assert(kFftElems < (1 << 21), "FFT workgroup indices must stay below 2^21 for small_div");
+
+// 1/d for small_div from the hardware reciprocal (within 1 ulp: the product
+// in small_div then stays inside the 2^-22 budget above)
+__device__ __forceinline__ float small_rcp(int d) { return __builtin_amdgcn_rcpf(static_cast<float>(d)); }
 static_assert(int64_t(kFftMaxLen / kTileX) * (kFftMaxLen / kTileY) * (kFftMaxLen / kTileZ) < (int64_t(1) << 31),
               "grid-1 tiles of a sub-problem must fit 31 bits");
 
@@ -400,9 +404,9 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int ls, int p, const cplx
     constexpr int MAXB = (fft_elems(NT) / R + NT - 1) / NT;
     const int nbf = n / R;
     const int total = nl * nbf;
-    const int twstep = n / (p * R);
+    const int twstep = small_div(n, small_rcp(p * R));   // exact: p R divides n
     const int pR = p * R;
-    const float rnbf = 1.0f / static_cast<float>(nbf), rp = 1.0f / static_cast<float>(p);
+    const float rnbf = small_rcp(nbf), rp = small_rcp(p);
     cplx<T> v[MAXB][R];
     int obase[MAXB];
 #pragma unroll
@@ -417,9 +421,9 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int ls, int p, const cplx
             const int tk = __mul24(k, twstep);
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                cplx<T> u = lds[lb + i + q * nbf];
+                cplx<T> u = lds[lb + i + __mul24(q, nbf)];
                 // exponent q k twstep < n; the LDS table holds exp(s 2 pi i j/n), j < n
-                if (q > 0) u = cmul<T>(u, tw[q * tk]);
+                if (q > 0) u = cmul<T>(u, tw[__mul24(q, tk)]);
                 v[c][q] = u;
             }
             dft_small<T, R>(v[c], s);
@@ -430,7 +434,7 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int ls, int p, const cplx
     for (int c = 0; c < MAXB; ++c) {
         if (obase[c] >= 0) {
 #pragma unroll
-            for (int m = 0; m < R; ++m) lds[obase[c] + m * p] = v[c][m];
+            for (int m = 0; m < R; ++m) lds[obase[c] + __mul24(m, p)] = v[c][m];
         }
     }
     __syncthreads();
@@ -499,7 +503,7 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
     if (pass < 2) {
         const cplx<T> *sb = src + line0 * nin;
         const T *px = precor + P.precor[0] + half_in;
-        const float rn = 1.0f / static_cast<float>(n);
+        const float rn = small_rcp(n);
         T fx[EPT];             // x pre-correction (pass x), applied after all loads are issued
         int jl[EPT], slot[EPT];
 #pragma unroll
@@ -527,7 +531,7 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
         }
     } else {
         const cplx<T> *sb = src + line0;
-        const float rl = 1.0f / static_cast<float>(nl);
+        const float rl = small_rcp(nl);
         int slot[EPT];
 #pragma unroll
         for (int c = 0; c < EPT; ++c) {
@@ -558,7 +562,7 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
     }
     // kept window: wstart is 0 (whole line) or -R with 2R < n, so wstart + q lies in (-n, n)
     cplx<T> *out = dst + line0 * wcnt;
-    const float rw = 1.0f / static_cast<float>(wcnt);
+    const float rw = small_rcp(wcnt);
     for (int e = threadIdx.x; e < nl * wcnt; e += NT) {
         const int j = small_div(e, rw), q = e - __mul24(j, wcnt);
         int m = wst + q;
