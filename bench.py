@@ -209,13 +209,16 @@ def main():
     ap.add_argument("--f64-steps", type=int, default=0, help="timed float64 steps (default: max(1, steps // 5))")
     ap.add_argument("--direct-threshold", type=float, default=-1.0,
                     help="per-sub-problem NUFFT/direct choice: <0 automatic (default), 0 forced NUFFT, inf all direct")
-    ap.add_argument("--serving", action="store_true", help="also run the 64-request serving workload (p50/p99)")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the 64-request serving workload (p50/p99); the default unless --no-modes")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     ap.add_argument("--skip-f64", action="store_true", help="time the float32 plan only")
     ap.add_argument("--n-pix", type=int, default=1000000,
                     help="sky points of the SKA-like workload (default the full 1,000,000-point cap; smaller "
                          "values only for counter runs, never for the reported metric)")
     ap.add_argument("--no-modes", action="store_true",
-                    help="skip the forced-NUFFT and all-direct float32 runs reported beside the headline")
+                    help="skip the runs reported beside the headline (forced NUFFT, all direct, four rows, the dense "
+                         "mesh, serving)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes three times (counter calibration)")
     args = ap.parse_args()
@@ -355,7 +358,7 @@ def main():
                         roofs[k]["traffic_frac"] = round(rf["traffic"] / avg_s / 1e9 / HBM_PEAK_GBS, 4)
             ent["rooflines"] = roofs
             out["modes"][m] = ent
-    if args.serving:
+    if args.serving or not (args.no_serving or args.no_modes):
         out["serving"] = serving_run()
     if not args.no_cpu_baseline:
         import oracle

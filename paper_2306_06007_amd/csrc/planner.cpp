@@ -484,6 +484,14 @@ double pair_nufft_seconds(const PairGeom &g, int64_t ns, int64_t nt, const Param
     return b / r.hbm_bytes_per_s + (ns * w3 + nt * w23) / r.cells_per_s + r.pair_overhead_s;
 }
 
+// lower bound of pair_nufft_seconds (no grid passes): fixed overhead and cell updates
+double nufft_seconds_floor(int64_t ns, int64_t nt, const Params &p)
+{
+    const Rates r = rates_for(p.dtype);
+    const double w3 = static_cast<double>(p.w) * p.w * p.w, w23 = static_cast<double>(p.w2) * p.w2 * p.w2;
+    return (ns * w3 + nt * w23) / r.cells_per_s + r.pair_overhead_s;
+}
+
 double pair_direct_seconds(int64_t ns, int64_t nt, int dtype)
 {
     return static_cast<double>(ns) * static_cast<double>(nt) / rates_for(dtype).terms_per_s;
@@ -504,7 +512,7 @@ double direct_rows_factor(int rows, int dtype)
 
 void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
                     std::map<std::pair<int32_t, int32_t>, int64_t> *precor_map,
-                    std::vector<double> *precor_nu, std::map<int32_t, int64_t> *tw_map)
+                    std::vector<double> *precor_nu, std::map<int32_t, int64_t> *tw_map, int64_t *max_pair_ws)
 {
     const Params &p = hp.prm;
     const ChunkSet &src = *in.src, &tgt = *in.tgt;
@@ -533,21 +541,33 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
         ranges.clear();
         for (int32_t i = 0; i < src.nc; ++i) {
             const int64_t ns = src.off[i + 1] - src.off[i];
-            PairGeom g = pair_geometry(&src.half[3 * i], S, p);
             // per call of ntrans_hint rows
-            double t_dir = pair_direct_seconds(ns, nt, p.dtype) * direct_rows_factor(p.ntrans_hint, p.dtype);
-            double t_nu = pair_nufft_seconds(g, ns, nt, p, nullptr) * p.ntrans_hint;
-            bool direct;
-            if (p.all_direct || !g.fits) direct = true;
-            else if (p.direct_threshold == 0.0) direct = false;
-            else if (p.direct_threshold < 0.0) direct = t_dir <= t_nu;
-            else direct = p.direct_threshold * t_dir <= t_nu;
-            if (direct) {
+            const double t_dir = pair_direct_seconds(ns, nt, p.dtype) * direct_rows_factor(p.ntrans_hint, p.dtype);
+            const double thr = p.direct_threshold < 0.0 ? 1.0 : p.direct_threshold;
+            // a NUFFT sub-problem costs at least its fixed overhead and its kernel-cell
+            // updates: a pair cheaper direct than that bound is direct whatever its grids
+            // (wide fields with thousands of small chunks skip the grid sizing)
+            const bool clearly_direct = p.all_direct ||
+                (p.direct_threshold != 0.0 && thr * t_dir <= nufft_seconds_floor(ns, nt, p) * p.ntrans_hint);
+            auto take_direct = [&]() {
                 dp->est_seconds += t_dir;
                 dp->direct_terms += static_cast<double>(ns) * nt;
-                if (ns == 0) continue;
+                if (ns == 0) return;
                 if (!ranges.empty() && ranges.back().second == src.off[i]) ranges.back().second = src.off[i + 1];
                 else ranges.emplace_back(src.off[i], src.off[i + 1]);
+            };
+            if (clearly_direct) {
+                take_direct();
+                continue;
+            }
+            PairGeom g = pair_geometry(&src.half[3 * i], S, p);
+            const double t_nu = pair_nufft_seconds(g, ns, nt, p, nullptr) * p.ntrans_hint;
+            bool direct;
+            if (!g.fits) direct = true;
+            else if (p.direct_threshold == 0.0) direct = false;
+            else direct = thr * t_dir <= t_nu;
+            if (direct) {
+                take_direct();
             } else {
                 dp->est_seconds += t_nu;
                 nufft.push_back({i, j, g});
@@ -597,7 +617,11 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
     dp->spread_tiles.clear();
     dp->tiles_total = 0;
     for (int q = 0; q < 3; ++q) dp->pre_tiles[q].clear();
-    const int64_t cap = static_cast<int64_t>(hp.ws_elems);
+    // batches fill the caller's workspace cap, raised to the largest NUFFT sub-problem
+    int64_t max_ws = 0;
+    for (const Cand &c : nufft) max_ws = std::max(max_ws, ws_of(c.g));
+    *max_pair_ws = max_ws;
+    const int64_t cap = std::max(static_cast<int64_t>(hp.ws_elems), max_ws);
     size_t k = 0;
     while (k < nufft.size()) {
         Batch b;
@@ -855,27 +879,18 @@ int make_host_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t 
     s_floor(hp->sky, syn_in.s_floor);
     s_floor(hp->vis, ana_in.s_floor);
 
-    // workspace: the caller's cap, raised to the largest sub-problem
-    int64_t max_ws = 0;
-    for (const DirInputs *in : {&syn_in, &ana_in}) {
-        for (int32_t j = 0; j < in->tgt->nc; ++j) {
-            double S[3];
-            for (int d = 0; d < 3; ++d) S[d] = std::max(in->tgt->half[3 * j + d], in->s_floor[d]);
-            for (int32_t i = 0; i < in->src->nc; ++i) {
-                PairGeom g = pair_geometry(&in->src->half[3 * i], S, p);
-                if (g.fits) max_ws = std::max(max_ws, ws_of(g));
-            }
-        }
-    }
-    hp->max_pair_ws = max_ws;
-    hp->ws_elems = std::max<int64_t>(max_ws, static_cast<int64_t>(p.ws_cap / delta));
+    // workspace: the caller's cap (each direction raises its batching cap to its
+    // largest NUFFT sub-problem)
+    hp->ws_elems = static_cast<int64_t>(p.ws_cap / delta);
 
     std::map<std::pair<int32_t, int32_t>, int64_t> precor_map;
     std::map<int32_t, int64_t> tw_map;
     hp->precor_nu.clear();
-    plan_direction(*hp, syn_in, &hp->syn, &precor_map, &hp->precor_nu, &tw_map);
-    plan_direction(*hp, ana_in, &hp->ana, &precor_map, &hp->precor_nu, &tw_map);
+    int64_t max_ws_syn = 0, max_ws_ana = 0;
+    plan_direction(*hp, syn_in, &hp->syn, &precor_map, &hp->precor_nu, &tw_map, &max_ws_syn);
+    plan_direction(*hp, ana_in, &hp->ana, &precor_map, &hp->precor_nu, &tw_map, &max_ws_ana);
 
+    hp->max_pair_ws = std::max(max_ws_syn, max_ws_ana);
     // actual workspace: the largest batch
     int64_t used = 0;
     for (const DirPlan *dp : {&hp->syn, &hp->ana})
