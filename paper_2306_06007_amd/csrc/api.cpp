@@ -58,7 +58,6 @@ struct DevDir {
     int64_t *pre_pts = nullptr, *pre_tgts = nullptr, *pre_tiles[3] = {nullptr, nullptr, nullptr};
     DirectItem *direct = nullptr;
     double *deconv = nullptr;        // per chunk-order target
-    int64_t *pre_stiles = nullptr;   // per batch: tile prefix over its pairs
     int64_t *pre_ttiles = nullptr;   // per batch: transpose-tile prefix over its pairs
     int32_t *records = nullptr;      // source indices listed per tile (plan-resident binning)
     SpreadTile *spread_tiles = nullptr;   // spreading tiles of every batch (descriptor per workgroup)
@@ -311,7 +310,6 @@ int upload_dir(hvox_plan_s *pl, const DirPlan &dp, DevDir *dd, hipStream_t st)
     for (int q = 0; q < 3; ++q)
         if ((e = upload(pl, dp.pre_tiles[q], &dd->pre_tiles[q], st)) != hipSuccess) return HVOX_ERR_OOM;
     if ((e = upload(pl, dp.direct, &dd->direct, st)) != hipSuccess) return HVOX_ERR_OOM;
-    if ((e = upload(pl, dp.pre_stiles, &dd->pre_stiles, st)) != hipSuccess) return HVOX_ERR_OOM;
     if ((e = upload(pl, dp.pre_ttiles, &dd->pre_ttiles, st)) != hipSuccess) return HVOX_ERR_OOM;
     return HVOX_OK;
 }

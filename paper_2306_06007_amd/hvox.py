@@ -356,10 +356,15 @@ class Plan:
 
 
 def footprint_bound(n_vis: int, n_pix: int, dtype: str, workspace_bytes: float) -> float:
-    """Upper bound on a plan's device memory before planning: coordinates,
-    permutations, deconvolution factors and accumulator per point, the
-    workspace cap, and sub-problem tables (bounded generously).  The
-    accumulator holds four rows (the direct sum's row batch)."""
+    """Device memory of a plan estimated before planning: coordinates,
+    permutations, deconvolution factors and accumulator per point (the
+    accumulator holds four rows, the direct sum's row batch), the workspace
+    cap, and 64 MB for the sub-problem tables.  It bounds plans whose NUFFT
+    sub-problems stay small (the serving workload's); a plan that sends many
+    sources through NUFFT grids also holds their staged records (32 / 64 bytes
+    per source of its largest batch) and tile lists (4 bytes per source and
+    grid-1 tile it touches), which can exceed the 64 MB: its plan_info()
+    reports the exact resident bytes."""
     per_point = 24 + 4 + 8 + 16
     return float(per_point * (n_vis + n_pix) + 16 * 4 * max(n_vis, n_pix) + workspace_bytes + 64e6)
 
