@@ -61,6 +61,9 @@ struct DevDir {
     int64_t *pre_ttiles = nullptr;   // per batch: transpose-tile prefix over its pairs
     int32_t *records = nullptr;      // source indices listed per tile (plan-resident binning)
     SpreadTile *spread_tiles = nullptr;   // spreading tiles of every batch (descriptor per workgroup)
+    // per batch: descriptors of the further parts of crowded tiles, after the batch's
+    // list_cnt first parts (a second launch adds them once the first has stored)
+    std::vector<int64_t> spread_add_cnt;
 };
 
 struct TimedLaunch {
@@ -245,6 +248,12 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
                     return launch_spread<T>(pairs, dd.spread_tiles + b.list_off, b.list_cnt, dd.records, pl->stage,
                                             pl->ws, p.w, p.beta, st);
                 }));
+                const int64_t n_add = dd.spread_add_cnt[&b - dp.batches.data()];
+                if (n_add > 0)
+                    HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
+                        return launch_spread<T>(pairs, dd.spread_tiles + b.list_off + b.list_cnt, n_add, dd.records,
+                                                pl->stage, pl->ws, p.w, p.beta, st);
+                    }));
                 for (int pass = 0; pass < 3; ++pass) {
                     HVOX_TRY(timed(pl, HVOX_K_FFT_X + pass, st, [&] {
                         return launch_fft<T>(pairs, dd.pre_tiles[pass] + b.pre_tiles[pass], np, b.tiles[pass], pass,
@@ -352,19 +361,20 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
     // batches spread every tile (empty ones write zeros), which writes each cell
     // once instead of twice (the fill streams at ~6.5 TB/s, an empty tile of the
     // spreading kernel at ~4.5 TB/s, so the fill pays only below about a third)
+    // A crowded tile (more than kSpreadSplit sources) becomes a first part, stored
+    // with the batch's other tiles, and further parts that a second launch adds
+    // atomically on top.
     dp.spread_tiles.clear();
+    dd->spread_add_cnt.assign(dp.batches.size(), 0);
+    std::vector<SpreadTile> adds;
     const double delta = pl->hp.prm.dtype == HVOX_F64 ? 16.0 : 8.0;
     for (Batch &b : dp.batches) {
         const int64_t t0 = dp.pairs[b.pair0].tile0;
         int64_t nonempty = 0;
-        bool crowded = false;
-        for (int64_t t = 0; t < b.stiles; ++t) {
-            nonempty += counts[t0 + t] > 0;
-            crowded = crowded || counts[t0 + t] > kSpreadSplit;
-        }
-        // a batch with crowded tiles (split into atomically adding parts) needs the fill too
-        b.sparse = crowded || 3 * nonempty < b.stiles;
+        for (int64_t t = 0; t < b.stiles; ++t) nonempty += counts[t0 + t] > 0;
+        b.sparse = 3 * nonempty < b.stiles;
         b.list_off = static_cast<int64_t>(dp.spread_tiles.size());
+        adds.clear();
         double listed_cells = 0.0;
         for (int64_t i = 0; i < b.npairs; ++i) {
             const PairDev &pd = dp.pairs[b.pair0 + i];
@@ -378,21 +388,25 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
                         d.org[0] = static_cast<int16_t>(tx * kTileX);
                         d.org[1] = static_cast<int16_t>(ty * kTileY);
                         d.org[2] = static_cast<int16_t>(tz * kTileZ);
-                        d.flags = counts[gt] > kSpreadSplit ? kSpreadAdd : 0;
-                        int32_t done = 0;
-                        do {   // a crowded tile: parts of at most kSpreadSplit sources
-                            d.r0 = off[gt] + done;
-                            d.cnt = std::min(counts[gt] - done, kSpreadSplit);
-                            if (!(d.flags & kSpreadAdd)) d.cnt = counts[gt];
-                            dp.spread_tiles.push_back(d);
-                            done += d.cnt;
-                        } while (done < counts[gt]);
+                        d.r0 = off[gt];
+                        d.cnt = std::min(counts[gt], kSpreadSplit);
+                        d.flags = 0;
+                        dp.spread_tiles.push_back(d);
+                        for (int32_t done = d.cnt; done < counts[gt]; done += kSpreadSplit) {
+                            SpreadTile a = d;
+                            a.r0 = off[gt] + done;
+                            a.cnt = std::min(counts[gt] - done, kSpreadSplit);
+                            a.flags = kSpreadAdd;
+                            adds.push_back(a);
+                        }
                         listed_cells += static_cast<double>(std::min(kTileX, pd.n1[0] - tx * kTileX)) *
                                         std::min(kTileY, pd.n1[1] - ty * kTileY) *
                                         std::min(kTileZ, pd.n1[2] - tz * kTileZ);
                     }
         }
         b.list_cnt = static_cast<int64_t>(dp.spread_tiles.size()) - b.list_off;
+        dd->spread_add_cnt[&b - dp.batches.data()] = static_cast<int64_t>(adds.size());
+        dp.spread_tiles.insert(dp.spread_tiles.end(), adds.begin(), adds.end());
         if (!b.sparse) continue;
         // the fill writes the batch's grid-1 region, spreading only the listed tiles' cells
         dp.alg_bytes[HVOX_K_SPREAD] -= delta * (static_cast<double>(b.g_cnt) - listed_cells);

@@ -111,12 +111,12 @@ struct SpreadTile {
     int32_t cnt;                 // records of the tile (of this part of it, see flags)
     int32_t pair;                // sub-problem, as an index into its batch's pairs
     int16_t org[3];              // grid-1 cell of the tile's first corner
-    int16_t flags;               // kSpreadAdd: one of several parts of a crowded tile (adds atomically)
+    int16_t flags;               // kSpreadAdd: a further part of a crowded tile (adds atomically)
 };
 constexpr int16_t kSpreadAdd = 1;
 // a tile with more sources is split into parts of at most this many, one
-// workgroup each, that add into the zero-filled grid (dense sub-problems
-// would otherwise leave most CUs idle behind a few long tiles)
+// workgroup each: the first stores, the others add on top in a later launch
+// (dense sub-problems would otherwise leave most CUs idle behind a few long tiles)
 constexpr int32_t kSpreadSplit = 256;
 static_assert(sizeof(SpreadTile) == 24, "spreading tile descriptor layout");
 static_assert(kFftMaxLen < 32768, "tile corners are stored in 16 bits");

@@ -239,9 +239,9 @@ __device__ __forceinline__ void load8(const double *p, double v[8])
 // fall in its column with two wide LDS reads and 2 kTileZ FMAs per source, and
 // the whole tile is written once (no atomics; for a given plan the result is
 // deterministic).  A crowded tile (more than kSpreadSplit sources) is split
-// into parts, one workgroup each, that add their sums atomically into the
-// zero-filled grid (float atomics: the rounding order of those cells varies
-// from run to run).  The tile's sub-problem, corner and source list come from
+// into parts, one workgroup each: the first stores like any tile, the others
+// (a second launch) add their sums atomically on top (float atomics: the
+// rounding order of those cells varies from run to run).  The tile's sub-problem, corner and source list come from
 // one plan-time descriptor (the binning), each source's value and footprint
 // from the pre-phase pass.
 template <typename T>
