@@ -166,6 +166,28 @@ def test_ntrans_batch_equals_loop():
     assert oracle.rel_l2(Vb, Vref) <= 1e-6
 
 
+@pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
+def test_ntrans_hint_plans_match_oracle(dtype, eps):
+    """Plans weighed for one and for four rows per call split the sub-problems
+    differently between NUFFT grids and direct blocks; four-row calls through
+    either stay within eps of the oracle."""
+    wl = W.dense_dcos(1.0, ntrans=4)          # 95k vis x 130k pix: the hint moves its NUFFT pairs to direct
+    rv = W.sample_rows(wl.n_vis, 256, seed=61)
+    rp = W.sample_rows(wl.n_pix, 256, seed=62)
+    Vref = oracle.synthesis(wl.uvw, wl.xyz, wl.sky, rows=rv)
+    Iref = oracle.analysis(wl.uvw, wl.xyz, wl.vis, rows=rp)
+    splits = []
+    for hint in (1, 4):
+        with hv.Plan(wl.uvw, wl.xyz, eps, dtype, ntrans_hint=hint) as p:
+            V = _np(p.synthesis(_t(wl.sky, dtype)))[:, rv]
+            I = _np(p.analysis(_t(wl.vis, dtype)))[:, rp]
+            splits.append(p.info()["n_pairs_nufft"])
+        es, ea = oracle.rel_l2(V, Vref), oracle.rel_l2(I, Iref)
+        print(f"[ntrans hint {hint} {dtype}] syn={es:.3e} ana={ea:.3e} nufft={splits[-1]}", flush=True)
+        assert es <= eps and ea <= eps
+    assert splits[1] < splits[0]
+
+
 def test_permutation_invariance():
     wl = W.compact_disk(n_vis=800, n_pix=900)
     rng = np.random.default_rng(2)
