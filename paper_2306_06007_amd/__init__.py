@@ -3,8 +3,9 @@
 
 ``Plan(uvw, xyz, eps, dtype)`` plans the transforms; ``Plan.synthesis`` and
 ``Plan.analysis`` run them on torch GPU tensors.  ``autograd`` wraps them as
-differentiable functions and ``serve`` runs a continuous-batching request
-loop.  ``workloads`` generates seeded synthetic inputs."""
+differentiable functions, ``serve`` runs a continuous-batching request
+loop, and ``radio`` offers dirty2vis / vis2dirty on direction-cosine images.
+``workloads`` generates seeded synthetic inputs."""
 from .hvox import (EXPORTS, HvoxError, KERNELS, Plan, alg1, footprint_bound, kernel_params, load_library,
                    partition, rel_l2)
 
