@@ -224,3 +224,24 @@ def test_ntrans_hint_shifts_the_choice_towards_direct():
     assert i4["est_seconds"] > i1["est_seconds"]
     with pytest.raises(hv.HvoxError):
         hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True, ntrans_hint=-1)
+
+
+def test_automatic_choice_is_never_worse_than_either_pure_mode():
+    """Per pair the planner takes the cheaper of the two evaluations (pairs
+    whose direct cost is under the least a NUFFT sub-problem can cost skip the
+    grid sizing): the automatic estimate is at most the all-direct and the
+    all-NUFFT estimates, and a wide-field request with thousands of small chunks
+    comes out all direct."""
+    wl = W.ska_like(n_pix=200000, n_ant=120, n_times=30)
+    est = {}
+    for name, thr in (("auto", -1.0), ("direct", float("inf")), ("nufft", 0.0)):
+        with hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True, direct_threshold=thr) as p:
+            est[name] = p.info()["est_seconds"]
+    assert est["auto"] <= est["direct"] * (1 + 1e-12)
+    assert est["auto"] <= est["nufft"] * (1 + 1e-12)
+    req = next(r for r in W.serving_requests(seed=4) if r.layout == "lofar" and r.uvw.shape[0] > 200000)
+    with hv.Plan(req.uvw, req.xyz, 1e-4, "f32", host_only=True) as p:
+        info = p.info()
+    assert info["n_vis_chunks"] * info["n_sky_chunks"] > 100000
+    assert info["n_pairs_nufft"] == 0
+    assert info["direct_terms"] == float(req.uvw.shape[0]) * req.xyz.shape[0]
