@@ -219,6 +219,9 @@ def main():
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the runs reported beside the headline (forced NUFFT, all direct, four rows, the dense "
                          "mesh, serving)")
+    ap.add_argument("--lofar", action="store_true",
+                    help="also time the LOFAR-like wide-field workload (5.0M vis x 4M pix, 60-degree cap) in float32 "
+                         "at eps = 1e-4 and float64 at eps = 1e-9 (about two minutes more)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes three times (counter calibration)")
     args = ap.parse_args()
@@ -273,7 +276,7 @@ def main():
         info = plan.info()
         r = dict(sec=sec, steps=steps, warmup=warm, plan_s=plan_s, stats=st, info=info,
                  V=bufs[2][0].cpu().numpy(), I=bufs[3][0].cpu().numpy(), n_units=wl.n_vis + wl.n_pix,
-                 workload=wl.name, wl=wl)
+                 workload=wl.name, wl=wl, dtype=dtype)
         plan.free()
         del bufs
         torch.cuda.empty_cache()
@@ -298,6 +301,12 @@ def main():
         modes["dense_10km"] = run_mode("f32", 1e-4, args.direct_threshold, 1, 1, work=dense)
         modes["dense_10km_all_direct"] = run_mode("f32", 0.0, -1.0, 1, 0, work=dense)
         del dense
+    if args.lofar:
+        lofar = W.lofar_like()
+        log(f"workload {lofar.name}")
+        modes["lofar_f32"] = run_mode("f32", 1e-4, args.direct_threshold, 1, 1, work=lofar)
+        modes["lofar_f64"] = run_mode("f64", 1e-9, args.direct_threshold, 1, 0, work=lofar)
+        del lofar
 
     r32, r64 = results["f32"], results.get("f64")
     n_units = wl.n_vis + wl.n_pix
@@ -339,14 +348,14 @@ def main():
         for m, r in modes.items():
             rows = 4 if m == "batched_ntrans4" else 1
             ent = {"ms_per_step": r["sec"] * 1e3, "value": rows * r["n_units"] / r["sec"], "ntrans": rows,
-                   "workload": r["workload"],
+                   "workload": r["workload"], "dtype": r["dtype"],
                    "n_pairs_nufft": r["info"]["n_pairs_nufft"], "n_pairs_direct": r["info"]["n_pairs_direct"],
                    "kernels": {k: {"ms": round(v["ms"], 3), "launches": v["launches"]}
                                for k, v in r["stats"].items() if v["launches"]}}
             roofs = {}
             for k, v in r["stats"].items():
                 if v["launches"] and v["ms"] > 0 and (v["alg_bytes"] or k == "direct"):
-                    _, rf = roofline_entry(r["stats"], "f32", k, rows=rows, mode=m)
+                    _, rf = roofline_entry(r["stats"], r["dtype"], k, rows=rows, mode=m)
                     roofs[k] = {"bound": rf["bound"], "achieved": round(rf["achieved"], 1), "unit": rf["unit"],
                                 "frac": round(rf["frac"], 4)}
                     if "issue_bound" in rf:
