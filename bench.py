@@ -222,6 +222,10 @@ def main():
     ap.add_argument("--lofar", action="store_true",
                     help="also time the LOFAR-like wide-field workload (5.0M vis x 4M pix, 60-degree cap) in float32 "
                          "at eps = 1e-4 and float64 at eps = 1e-9 (about two minutes more)")
+    ap.add_argument("--workload", choices=("ska-like", "dense-10km"), default="ska-like",
+                    help="the workload of the reported step: the SKA-like 995k vis x 1M pix cap (default, the "
+                         "metric's workload) or the dense 30-degree DCOS mesh of the 10 km rung (238k vis x 10.24M "
+                         "pix), e.g. for kernel traces of that mesh alone")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes three times (counter calibration)")
     args = ap.parse_args()
@@ -250,7 +254,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": nbytes, "copies": 3}), flush=True)
         return
-    wl = W.ska_like(n_pix=args.n_pix)
+    dense_head = args.workload == "dense-10km"
+    wl = W.dense_dcos(10.0) if dense_head else W.ska_like(n_pix=args.n_pix)
+    head_mode = "dense_10km" if dense_head else "auto"   # key of the counter summaries of this step
     log(f"workload {wl.name}")
 
     def run_mode(dtype, eps, direct_threshold, steps, warm, ntrans=1, work=None):
@@ -294,6 +300,7 @@ def main():
         modes["all_direct"] = run_mode("f32", 0.0, -1.0, 1, 0)
         # ntrans = 4 data rows through one plan (e.g. channels or polarisations)
         modes["batched_ntrans4"] = run_mode("f32", 1e-4, args.direct_threshold, 1, 1, ntrans=4)
+    if not (args.no_modes or dense_head):
         # a dense 30-degree DCOS image of the paper's telescope-radius ladder (10 km rung,
         # 238k vis x 10.24M pixels): most terms go through NUFFT sub-problems
         dense = W.dense_dcos(10.0)
@@ -311,7 +318,11 @@ def main():
     r32, r64 = results["f32"], results.get("f64")
     n_units = wl.n_vis + wl.n_pix
     value = n_units / r32["sec"]
-    kname, roof = roofline_entry(r32["stats"], "f32")
+    if args.direct_threshold != 0 and args.direct_threshold >= 0:
+        head_mode = "threshold"          # no counter summaries are taken at other thresholds
+    elif args.direct_threshold == 0:
+        head_mode = "dense_10km_forced_nufft" if dense_head else "forced_nufft"
+    kname, roof = roofline_entry(r32["stats"], "f32", mode=head_mode)
     out = {
         "metric": METRIC,
         "value": value,
@@ -325,8 +336,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"ska-like {wl.n_vis} vis x {wl.n_pix} pix (200 antennas, 50 hour angles, "
-                               "10-deg Fibonacci cap), synthesis+analysis", "eps": 1e-4,
+        "config": {"workload": (f"dense 30-deg DCOS mesh, 10 km rung, {wl.n_vis} vis x {wl.n_pix} pix, "
+                                "synthesis+analysis" if dense_head else
+                                f"ska-like {wl.n_vis} vis x {wl.n_pix} pix (200 antennas, 50 hour angles, "
+                                "10-deg Fibonacci cap), synthesis+analysis"), "eps": 1e-4,
                    "n_vis": wl.n_vis, "n_pix": wl.n_pix, "ntrans": 1},
         "roofline": roof,
         "roofline_kernel": kname,
