@@ -14,6 +14,9 @@ The roofline entry is the kernel that takes the most time in the float32
 step, timed with HIP events on the stream it runs on.  The CPU baseline is
 the FP64 oracle on a bounded sample of output rows, extrapolated linearly.
 
+``--workload dense-10km`` reports the same line for the dense 30-degree DCOS
+mesh of the 10 km telescope radius (238,203 vis x 10,240,000 pix) instead.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
 from __future__ import annotations
