@@ -259,6 +259,34 @@ def test_ragged_tails():
             assert es <= 1e-9 and ea <= 1e-9, (m, n, thr, es, ea)
 
 
+def _clustered_inputs(rng):
+    """A 2,000-baseline disk plus 3,000 visibilities within 1e-3 wavelengths of
+    one uvw point, and a 2,000-point cap plus 6,000 sky points within 1e-7 of
+    one direction: each cluster lies inside one kernel footprint, so the grid
+    tiles it touches hold thousands of points in either direction."""
+    uvw = np.concatenate([W.uvw_disk(2000, 600.0, 20.0, rng),
+                          np.array([123.4, -77.7, 5.0]) + 1e-3 * rng.standard_normal((3000, 3))])
+    c = np.array([0.03, -0.02, 1.0])
+    c /= np.linalg.norm(c)
+    cl = c + 1e-7 * rng.standard_normal((6000, 3))
+    cl /= np.linalg.norm(cl, axis=1, keepdims=True)
+    xyz = np.concatenate([W.fibonacci_cap(2000, 6.0), cl])
+    return uvw, xyz, W.complex_normal(1, xyz.shape[0], rng), W.complex_normal(1, uvw.shape[0], rng)
+
+
+@pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
+@pytest.mark.parametrize("budget", [math.inf, 16e6])
+def test_crowded_tiles(dtype, eps, budget):
+    """Tiles holding far more sources than one spreading workgroup takes (256)
+    are split into parts, the further parts added atomically by a second
+    launch; the result still meets eps in both directions."""
+    uvw, xyz, sky, vis = _clustered_inputs(np.random.default_rng(29))
+    es, ea, info = both_directions(uvw, xyz, sky, vis, eps, dtype, direct_threshold=0.0, max_fft_bytes=budget)
+    _report(f"crowded {dtype} {eps:g} B={budget:g}", es, ea, info)
+    assert info["n_pairs_direct"] == 0
+    assert es <= eps and ea <= eps
+
+
 # ---- full-size SKA-like workload (995k x 1M), sampled rows -------------------------------
 @pytest.mark.slow
 @pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
