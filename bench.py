@@ -89,6 +89,32 @@ def time_steps(plan, bufs, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def direction_times(plan, bufs, runs):
+    """Device time of each direction: ``runs`` passes of synthesis then
+    analysis, with HIP events recorded on the stream the calls are enqueued on
+    between them; median, p10 and p90 of synthesis, analysis and their sum."""
+    import numpy as np
+    import torch
+    sky, vis, vout, sout = bufs
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(runs)]
+    torch.cuda.synchronize()
+    for e0, e1, e2 in ev:
+        e0.record()
+        plan.synthesis(sky, out=vout)
+        e1.record()
+        plan.analysis(vis, out=sout)
+        e2.record()
+    torch.cuda.synchronize()
+    out = {"runs": runs}
+    for key, pick in (("synthesis_ms", lambda e: e[0].elapsed_time(e[1])),
+                      ("analysis_ms", lambda e: e[1].elapsed_time(e[2])),
+                      ("step_ms", lambda e: e[0].elapsed_time(e[2]))):
+        t = np.array([pick(e) for e in ev])
+        out[key] = {"median": float(np.median(t)), "p10": float(np.percentile(t, 10)),
+                    "p90": float(np.percentile(t, 90))}
+    return out
+
+
 def kernel_table(plan, bufs):
     """One step with per-launch HIP events recorded on the stream the kernels
     run on; per-kernel totals."""
@@ -229,6 +255,9 @@ def main():
                     help="the workload of the reported step: the SKA-like 995k vis x 1M pix cap (default, the "
                          "metric's workload) or the dense 30-degree DCOS mesh of the 10 km rung (238k vis x 10.24M "
                          "pix), e.g. for kernel traces of that mesh alone")
+    ap.add_argument("--dist-runs", type=int, default=20,
+                    help="passes of synthesis then analysis timed one by one with HIP events for the per-direction "
+                         "median / p10 / p90 of the float32 and float64 plans (0: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes three times (counter calibration)")
     args = ap.parse_args()
@@ -262,11 +291,11 @@ def main():
     head_mode = "dense_10km" if dense_head else "auto"   # key of the counter summaries of this step
     log(f"workload {wl.name}")
 
-    def run_mode(dtype, eps, direct_threshold, steps, warm, ntrans=1, work=None):
+    def run_mode(dtype, eps, direct_threshold, steps, warm, ntrans=1, work=None, dist=0):
         wl_m = wl if work is None else work
-        return _run_mode(wl_m, dtype, eps, direct_threshold, steps, warm, ntrans)
+        return _run_mode(wl_m, dtype, eps, direct_threshold, steps, warm, ntrans, dist)
 
-    def _run_mode(wl, dtype, eps, direct_threshold, steps, warm, ntrans):
+    def _run_mode(wl, dtype, eps, direct_threshold, steps, warm, ntrans, dist):
         cd = torch.complex64 if dtype == "f32" else torch.complex128
         t0 = time.perf_counter()
         plan = hv.Plan(wl.uvw, wl.xyz, eps, dtype, direct_threshold=direct_threshold, ntrans_hint=ntrans)
@@ -282,19 +311,23 @@ def main():
         log(f"{dtype} eps={eps:g} direct_threshold={direct_threshold:g}: {sec * 1e3:.1f} ms/step over {steps} "
             f"steps (plan {plan_s:.1f}s)")
         st = kernel_table(plan, bufs)
+        dirs = direction_times(plan, bufs, dist) if dist > 0 else None
+        if dirs:
+            log(f"  per direction over {dist} runs (median ms): synthesis {dirs['synthesis_ms']['median']:.1f}, "
+                f"analysis {dirs['analysis_ms']['median']:.1f}")
         info = plan.info()
         r = dict(sec=sec, steps=steps, warmup=warm, plan_s=plan_s, stats=st, info=info,
                  V=bufs[2][0].cpu().numpy(), I=bufs[3][0].cpu().numpy(), n_units=wl.n_vis + wl.n_pix,
-                 workload=wl.name, wl=wl, dtype=dtype)
+                 workload=wl.name, wl=wl, dtype=dtype, directions=dirs)
         plan.free()
         del bufs
         torch.cuda.empty_cache()
         return r
 
-    results = {"f32": run_mode("f32", 1e-4, args.direct_threshold, args.steps, args.warmup)}
+    results = {"f32": run_mode("f32", 1e-4, args.direct_threshold, args.steps, args.warmup, dist=args.dist_runs)}
     if not args.skip_f64:
         results["f64"] = run_mode("f64", 1e-9, args.direct_threshold, args.f64_steps or max(1, args.steps // 5),
-                                  min(1, args.warmup))
+                                  min(1, args.warmup), dist=args.dist_runs)
     modes = {}
     if not args.no_modes:
         # the two other execution modes of the float32 transform: every sub-problem as a
@@ -357,6 +390,8 @@ def main():
                             "GB_s": round(v["alg_bytes"] / (v["ms"] * 1e6), 1) if v["ms"] > 0 and v["alg_bytes"] else None}
                         for k, v in results[d]["stats"].items() if v["launches"]} for d in results},
         "mode": {"direct_threshold": args.direct_threshold},
+        # device time per direction (HIP events), median / p10 / p90 over --dist-runs passes
+        "directions": {d: results[d]["directions"] for d in results if results[d]["directions"]} or None,
         "source_hash": kernel_source_hash(),
     }
     if modes:
