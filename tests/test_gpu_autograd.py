@@ -78,3 +78,51 @@ def test_gradcheck_small_complex():
     with hv.Plan(uvw, xyz, 1e-10, "f64", direct_threshold=0.0) as p:
         x = torch.tensor(rng.normal(size=30) + 1j * rng.normal(size=30), device="cuda", requires_grad=True)
         assert torch.autograd.gradcheck(lambda t: HvoxSynthesis.apply(t, p), (x,), eps=1e-6, atol=1e-6, rtol=1e-4)
+
+
+@pytest.mark.slow
+def test_gradient_full_size_sampled():
+    """The differentiation workload at full size: 995,000 SKA-like
+    visibilities and a 1,000,000-point cap; y = A x_true from the float64 path
+    (eps 1e-9) plus noise at 20 dB SNR; the float32 gradient at
+    x0 = x_true + 0.1 U[-1, 1] against (i) central differences of the loss,
+    accumulated in float64, along 8 seeded unit directions, held to the
+    eps * ||g|| that an eps-accurate gradient allows for a unit direction, and
+    (ii) the oracle's adjoint of the same residual on 4,096 sampled pixels."""
+    import torch
+    wl = W.ska_like()
+    rng = np.random.default_rng(5)
+    x_true = rng.random(wl.n_pix)
+    with hv.Plan(wl.uvw, wl.xyz, 1e-9, "f64") as p64:
+        Ax = p64.synthesis(torch.as_tensor(x_true[None]).to("cuda", torch.complex128))[0].cpu().numpy()
+    y = Ax + W.noise_for_snr(float(np.vdot(Ax, Ax).real), wl.n_vis, 20.0, rng)
+    x0 = x_true + 0.1 * rng.uniform(-1, 1, wl.n_pix)
+    eps = 1e-4
+    with hv.Plan(wl.uvw, wl.xyz, eps, "f32") as p:
+        y128 = torch.as_tensor(y).to("cuda", torch.complex128)
+        yt = y128.to(torch.complex64)
+        x = torch.tensor(x0, dtype=torch.float32, device="cuda", requires_grad=True)
+        V = HvoxSynthesis.apply(x, p)
+        (0.5 * (V - yt).abs().pow(2).sum()).backward()
+        g = x.grad.double().cpu().numpy()
+        r = (V.detach().reshape(-1).to(torch.complex128) - y128).cpu().numpy()
+
+        def loss(xv):
+            Vx = p.synthesis(torch.as_tensor(xv[None]).to("cuda", torch.complex64))[0]
+            return 0.5 * float((Vx.to(torch.complex128) - y128).abs().pow(2).sum())
+
+        gn = float(np.linalg.norm(g))
+        tau = 100.0   # central differences of a quadratic are exact at any step
+        for k in range(8):
+            d = rng.normal(size=wl.n_pix)
+            d /= np.linalg.norm(d)
+            fd = (loss(x0 + tau * d) - loss(x0 - tau * d)) / (2 * tau)
+            print(f"[full-size gradient] direction {k}: fd={fd:.6e} g.d={g @ d:.6e} |g|={gn:.3e}", flush=True)
+            assert abs(fd - g @ d) <= eps * gn, (k, fd, g @ d, gn)
+            # and, as measured, to 1e-3 of the directional derivative itself
+            assert abs(fd - g @ d) <= 1e-3 * abs(g @ d) + 1e-6 * gn, (k, fd, g @ d, gn)
+    rp = W.sample_rows(wl.n_pix, 4096, seed=61)
+    g_ref = oracle.analysis(wl.uvw, wl.xyz, r[None], rows=rp).real[0]
+    err = oracle.rel_l2(g[rp], g_ref)
+    print(f"[full-size gradient] sampled rel-l2 vs oracle adjoint {err:.3e}", flush=True)
+    assert err <= 2 * eps
