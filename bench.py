@@ -181,6 +181,18 @@ VALU_CYCLES_PER_TERM = {("f32", 1): 89 / 8, ("f32", 2): 105 / 16, ("f32", 3): 12
                         ("f64", 1): 338 / 8, ("f64", 2): 370 / 16, ("f64", 3): 402 / 24, ("f64", 4): 434 / 32}
 
 
+def host_cpu_model() -> str:
+    """The host processor's model name (Linux /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, target_s=12.0):
     """FP64 oracle on sampled rows of both directions, extrapolated linearly
     (the direct sum's cost is exactly linear in the number of output rows)."""
@@ -203,6 +215,7 @@ def cpu_baseline(wl, target_s=12.0):
     t_full = t_v * wl.n_vis / k + t_p * wl.n_pix / k
     value = (wl.n_vis + wl.n_pix) / t_full
     info = {"value": value, "unit": "(vis+pix)/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "host_cpu": host_cpu_model(), "host_cpu_count": os.cpu_count(),
             "sample": f"{k} sampled visibility rows ({t_v:.1f}s) and {k} sampled pixel rows ({t_p:.1f}s) "
                       f"of the full sums, extrapolated linearly to {wl.n_vis}+{wl.n_pix} rows"}
     return info, (rv, Vs), (rp, Is)

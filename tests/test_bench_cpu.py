@@ -108,3 +108,8 @@ def test_stale_summaries_are_not_reported(tmp_path, monkeypatch):
     assert bench.measured_traffic("spread", "f32", "auto") is None
     assert bench.measured_traffic("interp", "f32", "auto") == 2.0
     assert bench.measured_traffic("fft_x", "f32", "auto") is None
+
+
+def test_host_cpu_model_is_a_string():
+    m = bench.host_cpu_model()
+    assert isinstance(m, str) and m
