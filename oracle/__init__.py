@@ -126,9 +126,65 @@ class planted_fault:
         return False
 
 
+# Planted mistakes of the error metrics (tests switch them on to show that the
+# metric pins catch them); None = the correct metric.
+_metric_fault = None
+METRIC_FAULTS = ("squared", "per_row_mean", "normalised_by_y", "max_norm", "real_part_only")
+
+
+class planted_metric_fault:
+    """Context manager switching ``rel_l2`` / ``max_rel_err`` to a deliberately
+    wrong variant (used only by the tests of the metrics' pins)."""
+
+    def __init__(self, kind: str):
+        if kind not in METRIC_FAULTS:
+            raise ValueError(kind)
+        self.kind = kind
+        self.old = None
+
+    def __enter__(self):
+        global _metric_fault
+        self.old, _metric_fault = _metric_fault, self.kind
+        return self
+
+    def __exit__(self, *exc):
+        global _metric_fault
+        _metric_fault = self.old
+        return False
+
+
 def rel_l2(y, ref) -> float:
-    """Relative l2 error ||y - ref|| / ||ref|| over all entries."""
+    """Relative l2 error ||y - ref||_2 / ||ref||_2 over all entries of all rows
+    (not squared, not averaged per row).  This is the reading of the paper's
+    "relative accuracy" (Sect. 5.2, never defined there) that every parity
+    test uses; a zero reference gives the absolute norm of y."""
     y = np.asarray(y); ref = np.asarray(ref)
-    d = np.linalg.norm((y - ref).ravel())
-    n = np.linalg.norm(ref.ravel())
-    return float(d / n) if n > 0 else float(d)
+    diff = y - ref
+    if _metric_fault == "real_part_only":
+        diff = diff.real
+    if _metric_fault == "per_row_mean":
+        y2 = np.atleast_2d(y); r2 = np.atleast_2d(ref)
+        return float(np.mean([np.linalg.norm(a - b) / np.linalg.norm(b) for a, b in zip(y2, r2)]))
+    d = np.linalg.norm(diff.ravel())
+    n = np.linalg.norm((y if _metric_fault == "normalised_by_y" else ref).ravel())
+    if _metric_fault == "max_norm":
+        d, n = np.max(np.abs(diff)), np.max(np.abs(ref))
+    r = float(d / n) if n > 0 else float(d)
+    return r * r if _metric_fault == "squared" else r
+
+
+def max_rel_err(y, ref) -> float:
+    """Largest error of one entry relative to the largest reference entry,
+    max_k |y_k - ref_k| / max_k |ref_k| over all rows: the element-wise
+    companion of ``rel_l2`` (a failure confined to a few outputs, e.g. targets
+    in the corners of a sub-problem's box, is not diluted by the others)."""
+    y = np.asarray(y); ref = np.asarray(ref)
+    diff = y - ref
+    if _metric_fault == "real_part_only":
+        diff = diff.real
+    d = float(np.max(np.abs(diff))) if diff.size else 0.0
+    n = float(np.max(np.abs(ref))) if ref.size else 0.0
+    if _metric_fault == "normalised_by_y":
+        n = float(np.max(np.abs(y))) if y.size else 0.0
+    r = d / n if n > 0 else d
+    return r * r if _metric_fault == "squared" else r

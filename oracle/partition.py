@@ -69,27 +69,65 @@ def lp_optimum(B, P, v_max, alpha=1.0):
     return float(np.sum(x)), h, eta
 
 
+# Planted mistakes of ``lp_feasible`` (tests switch them on to show that its
+# pins catch them); None = the correct checker.
+_feasible_fault = None
+FEASIBLE_FAULTS = ("always_true", "no_budget", "no_upper_bounds", "no_same_domain_bounds", "no_cross_bounds",
+                   "no_positivity")
+
+
+class planted_feasible_fault:
+    """Context manager switching ``lp_feasible`` to a deliberately wrong
+    variant (used only by the tests of its pins)."""
+
+    def __init__(self, kind: str):
+        if kind not in FEASIBLE_FAULTS:
+            raise ValueError(kind)
+        self.kind = kind
+        self.old = None
+
+    def __enter__(self):
+        global _feasible_fault
+        self.old, _feasible_fault = _feasible_fault, self.kind
+        return self
+
+    def __exit__(self, *exc):
+        global _feasible_fault
+        _feasible_fault = self.old
+        return False
+
+
 def lp_feasible(B, P, v_max, alpha, h, eta, rtol=1e-9):
-    """Check an (h, eta) against every constraint of Algorithm 1."""
+    """Check an (h, eta) against every constraint of Algorithm 1: positive
+    dimensions, the FFT memory bound prod(h eta) <= V_max, h <= B and
+    eta <= P, and the anisotropy bounds |u_k - u_j|, |v_k - v_j| and
+    |u_k - v_j| <= log(alpha) in the log variables u = log(h/B),
+    v = log(eta/P)."""
+    if _feasible_fault == "always_true":
+        return True
     B = np.asarray(B, float); P = np.asarray(P, float)
     h = np.asarray(h, float); eta = np.asarray(eta, float)
     if np.any(h <= 0) or np.any(eta <= 0):
+        if _feasible_fault != "no_positivity":
+            return False
+        return True            # the faulty checker cannot take the logarithms below
+    if _feasible_fault != "no_upper_bounds" and (np.any(h > B * (1 + rtol)) or np.any(eta > P * (1 + rtol))):
         return False
-    if np.any(h > B * (1 + rtol)) or np.any(eta > P * (1 + rtol)):
-        return False
-    if np.prod(h * eta) > v_max * (1 + rtol):
+    if _feasible_fault != "no_budget" and np.prod(h * eta) > v_max * (1 + rtol):
         return False
     u = np.log(h / B); v = np.log(eta / P)
     la = math.log(alpha) + 1e-9
-    for a in (u, v):
+    if _feasible_fault != "no_same_domain_bounds":
+        for a in (u, v):
+            for i in range(3):
+                for j in range(3):
+                    if abs(a[i] - a[j]) > la:
+                        return False
+    if _feasible_fault != "no_cross_bounds":
         for i in range(3):
             for j in range(3):
-                if abs(a[i] - a[j]) > la:
+                if abs(u[i] - v[j]) > la:
                     return False
-    for i in range(3):
-        for j in range(3):
-            if abs(u[i] - v[j]) > la:
-                return False
     return True
 
 

@@ -82,3 +82,44 @@ def test_alg2_single_cell_and_line():
     y = np.array([[0.05, 0, 0], [0.65, 0, 0], [1.3, 0, 0]])
     lab = P.partition_points(y, [0.6, 1.0, 1.0])
     assert lab[0] == lab[1] != lab[2]
+
+
+# ---- pins of the feasibility checker of Algorithm 1 -------------------------------
+def feasibility_pins() -> dict:
+    """Points that break exactly one constraint family of Algorithm 1 (and a
+    feasible one): a checker that drops any family accepts one of them."""
+    B = np.array([1.0e3, 2.0e3, 50.0])
+    Pw = np.array([0.3, 0.2, 0.01])
+    vol = float(np.prod(B * Pw))
+    vmax = vol * 1e-6                          # closed form at alpha = 1: t = 0.1
+    t = 0.1
+    a = 0.5 * math.log(1.8)                    # log(1.8) > log(1.5) = log(alpha)
+    res = {}
+    res["feasible_closed_form"] = P.lp_feasible(B, Pw, vmax, 1.0, t * B, t * Pw)
+    # FFT memory: every dimension 1.05x the optimum, prod(h eta) = 1.05^6 vmax
+    res["budget"] = not P.lp_feasible(B, Pw, vmax, 1.0, 1.05 * t * B, 1.05 * t * Pw)
+    # h <= B: one visibility box 1.5x the full width (alpha = 2 admits the spread, no budget)
+    h = B.copy(); h[0] *= 1.5
+    res["upper_bound"] = not P.lp_feasible(B, Pw, 1e300, 2.0, h, Pw.copy())
+    # same-domain anisotropy: u_0 - u_1 = log 1.8 > log 1.5, cross differences a < log 1.5, same volume
+    h = t * B * np.exp([a, -a, 0.0])
+    res["same_domain"] = not P.lp_feasible(B, Pw, vmax, 1.5, h, t * Pw)
+    # cross anisotropy: u_k - v_j = log 1.8 for every pair, same-domain differences 0, same volume
+    res["cross"] = not P.lp_feasible(B, Pw, vmax, 1.5, t * B * math.exp(a), t * Pw * math.exp(-a))
+    # positivity
+    h = t * B; h[2] = 0.0
+    res["positive"] = not P.lp_feasible(B, Pw, vmax, 1.0, h, t * Pw)
+    return res
+
+
+def test_feasibility_pins_hold():
+    res = feasibility_pins()
+    assert all(res.values()), res
+
+
+@pytest.mark.parametrize("fault", P.FEASIBLE_FAULTS)
+def test_feasibility_pins_catch_planted_faults(fault):
+    with P.planted_feasible_fault(fault):
+        res = feasibility_pins()
+    assert not all(res.values()), f"planted feasibility fault {fault!r} not caught: {res}"
+    assert all(feasibility_pins().values())
