@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define HVOX_VERSION 100
+#define HVOX_VERSION 200
 
 /* error codes */
 #define HVOX_OK          0
@@ -63,8 +63,30 @@ typedef enum { HVOX_F32 = 0, HVOX_F64 = 1 } hvox_dtype;
 #define HVOX_PLAN_HOST_ONLY  0x2  /* plan on the host only (partition, pair sizes, costs); no device memory,
                                      transforms return HVOX_ERR_STATE.  For inspection and CPU tests */
 #define HVOX_TIMING          0x4  /* record HIP events around every kernel launch; see hvox_stats */
+#define HVOX_PREORDERED      0x8  /* data vectors are in the plan's chunk order (hvox_plan_permutation)
+                                     instead of user order: the gather and scatter through the
+                                     permutations are skipped.  Sect. 4 recommends re-ordering the data
+                                     once when a plan is reused for repeated transforms. */
+#define HVOX_DETERMINISTIC   0x10 /* bit-reproducible results: no floating-point atomics.  Spreading tiles
+                                     are never split and list their sources in index order, sub-problems
+                                     sharing a target chunk never run in the same launch, and direct-sum
+                                     blocks add into the accumulator layer by layer in a fixed order.
+                                     Slower on crowded grids and on plans with few target chunks. */
 
 typedef struct hvox_plan_s *hvox_plan_t;
+
+/* Device-memory hooks.  When both are set, every device allocation of a plan
+ * (its tables, workspace, staging and accumulator, and the temporaries of plan
+ * creation) goes through them, e.g. to a framework's caching allocator:
+ *   dev_alloc(bytes, ctx, stream) returns a device pointer aligned to at least
+ *     256 bytes, or NULL on failure (the plan call then fails with
+ *     HVOX_ERR_OOM and every block it obtained is handed back);
+ *   dev_free(ptr, bytes, ctx, stream) releases a block obtained from dev_alloc
+ *     (stream: the plan's last stream, already synchronised).
+ * Blocks are first used on the stream given to hvox_plan and later on the
+ * streams of the transform calls.  Neither hook may be set alone. */
+typedef void *(*hvox_alloc_fn)(size_t bytes, void *ctx, void *stream);
+typedef void (*hvox_free_fn)(void *ptr, size_t bytes, void *ctx, void *stream);
 
 /* Plan options.  A zero-initialised struct (or a NULL pointer) selects the
  * defaults noted on each field. */
@@ -89,11 +111,15 @@ typedef struct {
     const int32_t *vis_chunk; /* optional custom partition (host, [n_vis] chunk ids >= 0), replacing
                                  Algorithm 2 on the visibility domain (Sect. 4, allocate()). */
     const int32_t *sky_chunk; /* same for the sky domain ([n_pix]). */
-    int32_t flags;            /* HVOX_REAL_SKY | HVOX_PLAN_HOST_ONLY | HVOX_TIMING */
+    int32_t flags;            /* HVOX_REAL_SKY | HVOX_PLAN_HOST_ONLY | HVOX_TIMING | HVOX_PREORDERED |
+                                 HVOX_DETERMINISTIC */
     int32_t ntrans_hint;      /* data rows per call the NUFFT/direct choice is weighed for; 0 -> 1,
                                  negative -> HVOX_ERR_ARG.  The direct sum shares its phase factors
                                  among up to four rows while a NUFFT sub-problem repeats per row, so
                                  batched calls favour direct blocks.  Results never depend on it. */
+    hvox_alloc_fn dev_alloc;  /* optional device-memory hooks (see above); NULL -> hipMalloc / hipFree */
+    hvox_free_fn  dev_free;
+    void *alloc_ctx;          /* passed to both hooks */
 } hvox_opts;
 
 /* What a plan decided.  Sizes in bytes; counts of sub-problems are per
@@ -121,6 +147,12 @@ typedef struct {
     double  direct_terms;     /* sum over direct sub-problems of N_src * N_tgt */
     double  est_seconds;      /* cost-model estimate of one synthesis + one analysis (of ntrans_hint rows) */
     double  plan_seconds;     /* host + device time spent in hvox_plan */
+    int64_t device_bytes;     /* device memory the plan holds (resident + workspace); for a host-only
+                                 plan an upper bound of what hvox_plan_upload will allocate (exact but
+                                 for the tile lists, bounded by every source touching 2^3 tiles) */
+    int32_t flags;            /* the plan's option flags */
+    int32_t on_device;        /* 1 once the device part exists */
+    int64_t n_direct_layers;  /* HVOX_DETERMINISTIC: launches of the direct sum per data-row group */
 } hvox_plan_info_t;
 
 /* Per-kernel statistics of the calls since the last reset (HVOX_TIMING plans). */
@@ -155,10 +187,23 @@ typedef struct {
  * case).  eps floors: 1e-5 for HVOX_F32, 1e-10 for HVOX_F64.
  * n_vis or n_pix may be 0 (outputs are then all zero / empty).
  * On success *out receives the plan, owned by the caller (hvox_free).
+ * Out of memory (HVOX_ERR_OOM) leaves nothing allocated.  The environment
+ * variable HVOX_FORCE_OOM_BYTES (a byte count) makes every plan whose device
+ * memory would exceed it fail with HVOX_ERR_OOM, host-only plans included
+ * (their device_bytes bound is checked): fault injection for tests.
  */
 int hvox_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t n_pix,
               double eps, int32_t dtype, const hvox_opts *opts, void *stream,
               hvox_plan_t *out);
+
+/* Create the device part of a plan made with HVOX_PLAN_HOST_ONLY (a host
+ * plan, e.g. planned on a worker thread and admitted by its device_bytes):
+ * uploads coordinates and tables and allocates the workspace on `stream`
+ * (synchronised before return), exactly as hvox_plan would have.  The plan
+ * then runs transforms; its flags lose HVOX_PLAN_HOST_ONLY.  On failure the
+ * plan stays host-only and holds no device memory.  HVOX_ERR_STATE if the plan
+ * already has its device part. */
+int hvox_plan_upload(hvox_plan_t plan, void *stream);
 
 /* sky -> vis:  vis[t][k] = sum_n sky[t][n] exp(-2 pi i <p_k, r_n>)   (Eq. 2)
  * sky: device [ntrans][n_pix] complex, vis: device [ntrans][n_vis] complex.

@@ -6,8 +6,8 @@
 differentiable functions, ``serve`` runs a continuous-batching request
 loop, and ``radio`` offers dirty2vis / vis2dirty on direction-cosine images.
 ``workloads`` generates seeded synthetic inputs."""
-from .hvox import (EXPORTS, HvoxError, KERNELS, Plan, alg1, footprint_bound, kernel_params, load_library,
+from .hvox import (EXPORTS, HvoxError, KERNELS, Plan, alg1, kernel_params, load_library,
                    partition, rel_l2)
 
-__all__ = ["EXPORTS", "HvoxError", "KERNELS", "Plan", "alg1", "footprint_bound", "kernel_params",
+__all__ = ["EXPORTS", "HvoxError", "KERNELS", "Plan", "alg1", "kernel_params",
            "load_library", "partition", "rel_l2"]

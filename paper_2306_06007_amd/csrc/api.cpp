@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <new>
@@ -36,10 +37,10 @@ template <typename T>
 hipError_t launch_transpose(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
 template <typename T>
 hipError_t launch_interp(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t, const double *,
-                         const void *, double *, int, double, double, hipStream_t);
+                         const void *, double *, int, double, double, int, hipStream_t);
 template <typename T>
 hipError_t launch_direct(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
-                         const int32_t *, const void *, int64_t, double *, int64_t, int, double, hipStream_t);
+                         const int32_t *, const void *, int64_t, double *, int64_t, int, double, int, hipStream_t);
 template <typename T>
 hipError_t launch_finalize(const double *, int64_t, const int32_t *, void *, int, hipStream_t);
 
@@ -79,7 +80,13 @@ struct hvox_plan_s {
     bool host_only = false;
     int device = 0;
     size_t resident_bytes = 0;
-    std::vector<void *> allocations;
+    size_t device_bytes = 0;                            // every live device block of the plan
+    std::vector<std::pair<void *, size_t>> allocations;
+    hvox_alloc_fn alloc_hook = nullptr;                 // caller's device-memory hooks (or NULL)
+    hvox_free_fn free_hook = nullptr;
+    void *alloc_ctx = nullptr;
+    double oom_limit = -1.0;                            // HVOX_FORCE_OOM_BYTES at plan creation (< 0: none)
+    size_t alloc_peak = 0;                              // device bytes obtained so far (incl. temporaries)
     double *vis_xyz = nullptr, *sky_xyz = nullptr;     // SoA [3][n], chunk order
     int32_t *vis_perm = nullptr, *sky_perm = nullptr;
     void *precor = nullptr;                             // pre-correction tables in the plan's precision
@@ -99,35 +106,62 @@ struct hvox_plan_s {
 namespace hvox {
 namespace {
 
+// One device block through the caller's hooks or hipMalloc, refused beyond the
+// HVOX_FORCE_OOM_BYTES limit (fault injection).  Temporaries are handed back
+// with raw_free; plan blocks are listed and released with the plan.
+hipError_t raw_alloc(hvox_plan_s *pl, size_t bytes, void **dst, hipStream_t st)
+{
+    *dst = nullptr;
+    if (pl->oom_limit >= 0.0 && static_cast<double>(pl->device_bytes + bytes) > pl->oom_limit)
+        return hipErrorOutOfMemory;
+    if (pl->alloc_hook) {
+        *dst = pl->alloc_hook(bytes, pl->alloc_ctx, st);
+        if (!*dst) return hipErrorOutOfMemory;
+    } else {
+        hipError_t e = hipMalloc(dst, bytes);
+        if (e != hipSuccess) { *dst = nullptr; return e; }
+    }
+    pl->device_bytes += bytes;
+    pl->alloc_peak = std::max(pl->alloc_peak, pl->device_bytes);
+    return hipSuccess;
+}
+
+void raw_free(hvox_plan_s *pl, void *p, size_t bytes, hipStream_t st)
+{
+    if (!p) return;
+    if (pl->free_hook) pl->free_hook(p, bytes, pl->alloc_ctx, st);
+    else (void)hipFree(p);
+    pl->device_bytes -= bytes;
+}
+
+hipError_t dev_alloc(hvox_plan_s *pl, size_t bytes, void **dst, bool resident, hipStream_t st)
+{
+    *dst = nullptr;
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = raw_alloc(pl, bytes, dst, st);
+    if (e != hipSuccess) return e;
+    pl->allocations.emplace_back(*dst, bytes);
+    if (resident) pl->resident_bytes += bytes;
+    return hipSuccess;
+}
+
 template <typename V>
 hipError_t upload(hvox_plan_s *pl, const std::vector<V> &v, V **dst, hipStream_t st)
 {
     *dst = nullptr;
     if (v.empty()) return hipSuccess;
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, v.size() * sizeof(V));
+    hipError_t e = dev_alloc(pl, v.size() * sizeof(V), &p, true, st);
     if (e != hipSuccess) return e;
-    pl->allocations.push_back(p);
-    pl->resident_bytes += v.size() * sizeof(V);
     *dst = static_cast<V *>(p);
     return hipMemcpyAsync(p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, st);
 }
 
-hipError_t dev_alloc(hvox_plan_s *pl, size_t bytes, void **dst, bool resident)
-{
-    *dst = nullptr;
-    if (bytes == 0) return hipSuccess;
-    hipError_t e = hipMalloc(dst, bytes);
-    if (e != hipSuccess) return e;
-    pl->allocations.push_back(*dst);
-    if (resident) pl->resident_bytes += bytes;
-    return hipSuccess;
-}
-
 void release(hvox_plan_s *pl)
 {
-    for (void *p : pl->allocations) (void)hipFree(p);
+    for (auto &a : pl->allocations) raw_free(pl, a.first, a.second, pl->last_stream);
     pl->allocations.clear();
+    pl->resident_bytes = 0;
     for (auto &t : pl->pending) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
     pl->pending.clear();
     for (hipEvent_t e : pl->spare_events) (void)hipEventDestroy(e);
@@ -180,11 +214,13 @@ hipError_t resolve_timing(hvox_plan_s *pl)
     return hipSuccess;
 }
 
+// Launch f(), bracketed by HIP events on st when the plan times its kernels and
+// the caller allows it (the allocation-free entry point never creates events).
 template <class F>
-hipError_t timed(hvox_plan_s *pl, int kind, hipStream_t st, F &&f)
+hipError_t timed(hvox_plan_s *pl, bool may_time, int kind, hipStream_t st, F &&f)
 {
     pl->stats.launches[kind] += 1;
-    if (!(pl->hp.prm.flags & HVOX_TIMING)) return f();
+    if (!may_time || !(pl->hp.prm.flags & HVOX_TIMING)) return f();
     hipEvent_t a = take_event(pl), b = take_event(pl);
     if (!a || !b) return hipErrorOutOfMemory;
     hipError_t e = hipEventRecord(a, st);
@@ -195,9 +231,19 @@ hipError_t timed(hvox_plan_s *pl, int kind, hipStream_t st, F &&f)
     return e;
 }
 
+// Device buffers a transform works in besides its inputs and outputs: the
+// grid workspace, the staged sources of one batch, and the float64
+// accumulator rows (kRowBatch rows of the larger domain).
+struct Scratch {
+    void *ws;
+    void *stage;
+    double *acc;
+};
+
 // ---- executor -----------------------------------------------------------------
 template <typename T>
-int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, int32_t ntrans, hipStream_t st)
+int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, int32_t ntrans, hipStream_t st,
+                  const Scratch &sc, bool may_time)
 {
     const HostPlan &hp = pl->hp;
     const Params &p = hp.prm;
@@ -207,10 +253,13 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
     const int64_t n_tgt = synthesis ? hp.n_vis : hp.n_pix;
     const double *sxyz = synthesis ? pl->sky_xyz : pl->vis_xyz;
     const double *txyz = synthesis ? pl->vis_xyz : pl->sky_xyz;
-    const int32_t *sperm = synthesis ? pl->sky_perm : pl->vis_perm;
-    const int32_t *tperm = synthesis ? pl->vis_perm : pl->sky_perm;
+    // data already in chunk order: no gather / scatter through the permutations
+    const bool pre = (p.flags & HVOX_PREORDERED) != 0;
+    const int32_t *sperm = pre ? nullptr : (synthesis ? pl->sky_perm : pl->vis_perm);
+    const int32_t *tperm = pre ? nullptr : (synthesis ? pl->vis_perm : pl->sky_perm);
     const double iota = synthesis ? -1.0 : 1.0;
     const int real_only = (!synthesis && (p.flags & HVOX_REAL_SKY)) ? 1 : 0;
+    const int det = p.deterministic() ? 1 : 0;
     using C = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
     hipError_t e = hipSuccess;
 #define HVOX_TRY(expr)                                                                             \
@@ -225,63 +274,66 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
     for (int32_t t0 = 0; t0 < ntrans; t0 += kRowBatch) {
         const int nb = static_cast<int>(std::min<int32_t>(kRowBatch, ntrans - t0));
         if (n_tgt == 0) continue;
-        HVOX_TRY(timed(pl, HVOX_K_ZERO, st, [&] { return launch_zero(pl->acc, 2 * n_tgt * nb, st); }));
+        HVOX_TRY(timed(pl, may_time, HVOX_K_ZERO, st, [&] { return launch_zero(sc.acc, 2 * n_tgt * nb, st); }));
         for (int r = 0; r < nb; ++r) {
             const C *in_t = static_cast<const C *>(in) + static_cast<int64_t>(t0 + r) * n_src;
-            double *acc_r = pl->acc + 2 * n_tgt * r;
+            double *acc_r = sc.acc + 2 * n_tgt * r;
             for (const Batch &b : dp.batches) {
                 const PairDev *pairs = dd.pairs + b.pair0;
                 const int np = static_cast<int>(b.npairs);
                 const int64_t *pprefix = dd.pre_pts + b.pre_pts;
-                HVOX_TRY(timed(pl, HVOX_K_PREPHASE, st, [&] {
-                    return launch_prephase<T>(pairs, pprefix, np, b.pts, sxyz, n_src, sperm, in_t, pl->stage, iota,
+                HVOX_TRY(timed(pl, may_time, HVOX_K_PREPHASE, st, [&] {
+                    return launch_prephase<T>(pairs, pprefix, np, b.pts, sxyz, n_src, sperm, in_t, sc.stage, iota,
                                               p.w, st);
                 }));
                 if (b.sparse) {
                     // mostly empty grid 1: clear the batch's grid-1 region, then spread the listed tiles
-                    HVOX_TRY(timed(pl, HVOX_K_ZERO, st, [&] {
-                        return launch_zero(static_cast<double *>(pl->ws),
+                    HVOX_TRY(timed(pl, may_time, HVOX_K_ZERO, st, [&] {
+                        return launch_zero(static_cast<double *>(sc.ws),
                                            b.g_cnt * static_cast<int64_t>(sizeof(C) / sizeof(double)), st);
                     }));
                 }
-                HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
-                    return launch_spread<T>(pairs, dd.spread_tiles + b.list_off, b.list_cnt, dd.records, pl->stage,
-                                            pl->ws, p.w, p.beta, st);
+                HVOX_TRY(timed(pl, may_time, HVOX_K_SPREAD, st, [&] {
+                    return launch_spread<T>(pairs, dd.spread_tiles + b.list_off, b.list_cnt, dd.records, sc.stage,
+                                            sc.ws, p.w, p.beta, st);
                 }));
                 const int64_t n_add = dd.spread_add_cnt[&b - dp.batches.data()];
                 if (n_add > 0)
-                    HVOX_TRY(timed(pl, HVOX_K_SPREAD, st, [&] {
+                    HVOX_TRY(timed(pl, may_time, HVOX_K_SPREAD, st, [&] {
                         return launch_spread<T>(pairs, dd.spread_tiles + b.list_off + b.list_cnt, n_add, dd.records,
-                                                pl->stage, pl->ws, p.w, p.beta, st);
+                                                sc.stage, sc.ws, p.w, p.beta, st);
                     }));
                 for (int pass = 0; pass < 3; ++pass) {
-                    HVOX_TRY(timed(pl, HVOX_K_FFT_X + pass, st, [&] {
+                    HVOX_TRY(timed(pl, may_time, HVOX_K_FFT_X + pass, st, [&] {
                         return launch_fft<T>(pairs, dd.pre_tiles[pass] + b.pre_tiles[pass], np, b.tiles[pass], pass,
-                                             pl->ws, pl->tw, pl->precor, b.lds_elems[pass], b.max_pass_len[pass],
+                                             sc.ws, pl->tw, pl->precor, b.lds_elems[pass], b.max_pass_len[pass],
                                              iota, st);
                     }));
                     if (pass == 0)
-                        HVOX_TRY(timed(pl, HVOX_K_TRANSPOSE, st, [&] {
-                            return launch_transpose<T>(pairs, dd.pre_ttiles + b.pre_ttiles, np, b.ttiles, pl->ws,
-                                                       st);
+                        HVOX_TRY(timed(pl, may_time, HVOX_K_TRANSPOSE, st, [&] {
+                            return launch_transpose<T>(pairs, dd.pre_ttiles + b.pre_ttiles, np, b.ttiles, sc.ws, st);
                         }));
                 }
-                HVOX_TRY(timed(pl, HVOX_K_INTERP, st, [&] {
+                HVOX_TRY(timed(pl, may_time, HVOX_K_INTERP, st, [&] {
                     return launch_interp<T>(pairs, dd.pre_tgts + b.pre_tgts, np, b.iblocks, txyz, n_tgt, dd.deconv,
-                                            pl->ws, acc_r, p.w2, p.beta2, iota, st);
+                                            sc.ws, acc_r, p.w2, p.beta2, iota, det, st);
                 }));
             }
         }
-        if (!dp.direct.empty())
-            HVOX_TRY(timed(pl, HVOX_K_DIRECT, st, [&] {
-                return launch_direct<T>(dd.direct, static_cast<int64_t>(dp.direct.size()), sxyz, n_src, txyz, n_tgt,
-                                        sperm, static_cast<const C *>(in) + static_cast<int64_t>(t0) * n_src, n_src,
-                                        pl->acc, 2 * n_tgt, nb, iota, st);
+        // direct blocks: one launch, or (deterministic plans) one launch per layer of
+        // items that share no target, in a fixed order
+        for (size_t l = 0; l + 1 < dp.direct_layer_off.size(); ++l) {
+            const int64_t i0 = dp.direct_layer_off[l], i1 = dp.direct_layer_off[l + 1];
+            HVOX_TRY(timed(pl, may_time, HVOX_K_DIRECT, st, [&] {
+                return launch_direct<T>(dd.direct + i0, i1 - i0, sxyz, n_src, txyz, n_tgt, sperm,
+                                        static_cast<const C *>(in) + static_cast<int64_t>(t0) * n_src, n_src, sc.acc,
+                                        2 * n_tgt, nb, iota, det, st);
             }));
+        }
         for (int r = 0; r < nb; ++r) {
             C *out_t = static_cast<C *>(out) + static_cast<int64_t>(t0 + r) * n_tgt;
-            HVOX_TRY(timed(pl, HVOX_K_FINAL, st, [&] {
-                return launch_finalize<T>(pl->acc + 2 * n_tgt * r, n_tgt, tperm, out_t, real_only, st);
+            HVOX_TRY(timed(pl, may_time, HVOX_K_FINAL, st, [&] {
+                return launch_finalize<T>(sc.acc + 2 * n_tgt * r, n_tgt, tperm, out_t, real_only, st);
             }));
         }
         for (int k = 0; k < HVOX_K_COUNT; ++k) {
@@ -297,7 +349,7 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
 int transform(hvox_plan_s *pl, bool synthesis, const void *in, void *out, int32_t ntrans, void *stream)
 {
     if (!pl) return fail(HVOX_ERR_STATE, "NULL plan");
-    if (pl->host_only) return fail(HVOX_ERR_STATE, "host-only plan cannot run transforms");
+    if (pl->host_only) return fail(HVOX_ERR_STATE, "host-only plan cannot run transforms (hvox_plan_upload first)");
     if (ntrans < 1) return fail(HVOX_ERR_ARG, "ntrans must be >= 1");
     const int64_t n_in = synthesis ? pl->hp.n_pix : pl->hp.n_vis;
     const int64_t n_out = synthesis ? pl->hp.n_vis : pl->hp.n_pix;
@@ -306,8 +358,9 @@ int transform(hvox_plan_s *pl, bool synthesis, const void *in, void *out, int32_
     if (hipGetDevice(&cur) != hipSuccess) return fail(HVOX_ERR_HIP, "hipGetDevice failed");
     if (cur != pl->device) return fail(HVOX_ERR_STATE, "the plan's device is not the current device");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (pl->hp.prm.dtype == HVOX_F64) return run_direction<double>(pl, synthesis, in, out, ntrans, st);
-    return run_direction<float>(pl, synthesis, in, out, ntrans, st);
+    const Scratch sc{pl->ws, pl->stage, pl->acc};
+    if (pl->hp.prm.dtype == HVOX_F64) return run_direction<double>(pl, synthesis, in, out, ntrans, st, sc, true);
+    return run_direction<float>(pl, synthesis, in, out, ntrans, st, sc, true);
 }
 
 int upload_dir(hvox_plan_s *pl, const DirPlan &dp, DevDir *dd, hipStream_t st)
@@ -331,18 +384,21 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
 {
     if (dp.tiles_total == 0) return HVOX_OK;
     const int w = pl->hp.prm.w;
+    const bool det = pl->hp.prm.deterministic();
     const int64_t nt = dp.tiles_total;
     void *d_counts = nullptr, *d_cursor = nullptr;
     auto cleanup = [&]() {
-        if (d_counts) (void)hipFree(d_counts);
-        if (d_cursor) (void)hipFree(d_cursor);
+        (void)hipStreamSynchronize(st);
+        raw_free(pl, d_counts, sizeof(int32_t) * nt, st);
+        raw_free(pl, d_cursor, sizeof(unsigned long long) * nt, st);
+        d_counts = d_cursor = nullptr;
     };
     auto bad = [&](hipError_t e, const char *what) {
         cleanup();
         *err = std::string(what) + ": " + hipGetErrorString(e);
         return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? HVOX_ERR_OOM : HVOX_ERR_HIP;
     };
-    hipError_t e = hipMalloc(&d_counts, sizeof(int32_t) * nt);
+    hipError_t e = raw_alloc(pl, sizeof(int32_t) * nt, &d_counts, st);
     if (e != hipSuccess) return bad(e, "binning counts");
     e = hipMemsetAsync(d_counts, 0, sizeof(int32_t) * nt, st);
     for (const Batch &b : dp.batches) {
@@ -363,7 +419,8 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
     // spreading kernel at ~4.5 TB/s, so the fill pays only below about a third)
     // A crowded tile (more than kSpreadSplit sources) becomes a first part, stored
     // with the batch's other tiles, and further parts that a second launch adds
-    // atomically on top.
+    // atomically on top -- except in deterministic plans, whose tiles are never split.
+    const int32_t split = det ? INT32_MAX : kSpreadSplit;
     dp.spread_tiles.clear();
     dd->spread_add_cnt.assign(dp.batches.size(), 0);
     std::vector<SpreadTile> adds;
@@ -389,13 +446,13 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
                         d.org[1] = static_cast<int16_t>(ty * kTileY);
                         d.org[2] = static_cast<int16_t>(tz * kTileZ);
                         d.r0 = off[gt];
-                        d.cnt = std::min(counts[gt], kSpreadSplit);
+                        d.cnt = std::min(counts[gt], split);
                         d.flags = 0;
                         dp.spread_tiles.push_back(d);
-                        for (int32_t done = d.cnt; done < counts[gt]; done += kSpreadSplit) {
+                        for (int32_t done = d.cnt; done < counts[gt]; done += split) {
                             SpreadTile a = d;
                             a.r0 = off[gt] + done;
-                            a.cnt = std::min(counts[gt] - done, kSpreadSplit);
+                            a.cnt = std::min(counts[gt] - done, split);
                             a.flags = kSpreadAdd;
                             adds.push_back(a);
                         }
@@ -420,10 +477,10 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
         dp.spread_tiles.shrink_to_fit();
     }
     void *rec = nullptr;
-    e = dev_alloc(pl, sizeof(int32_t) * std::max<int64_t>(off[nt], 1), &rec, true);
+    e = dev_alloc(pl, sizeof(int32_t) * std::max<int64_t>(off[nt], 1), &rec, true, st);
     if (e != hipSuccess) return bad(e, "tile records");
     dd->records = static_cast<int32_t *>(rec);
-    e = hipMalloc(&d_cursor, sizeof(unsigned long long) * nt);
+    e = raw_alloc(pl, sizeof(unsigned long long) * nt, &d_cursor, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_cursor, off.data(), sizeof(int64_t) * nt, hipMemcpyHostToDevice, st);
     for (const Batch &b : dp.batches) {
@@ -433,6 +490,18 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return bad(e, "binning scatter pass");
+    if (det && off[nt] > 0) {
+        // the scatter lists a tile's sources in the order its atomics land; deterministic
+        // plans list them in index order, so every tile sums its sources in a fixed order
+        std::vector<int32_t> recs(off[nt]);
+        e = hipMemcpyAsync(recs.data(), rec, sizeof(int32_t) * off[nt], hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return bad(e, "tile records download");
+        for (int64_t t = 0; t < nt; ++t) std::sort(recs.begin() + off[t], recs.begin() + off[t + 1]);
+        e = hipMemcpyAsync(rec, recs.data(), sizeof(int32_t) * off[nt], hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return bad(e, "tile records upload");
+    }
     cleanup();
     return HVOX_OK;
 }
@@ -444,6 +513,11 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
     if (hipGetDevice(&pl->device) != hipSuccess) { *err = "hipGetDevice failed"; return HVOX_ERR_HIP; }
     std::vector<double> vx = soa(hp.uvw, hp.vis.perm), sx = soa(hp.xyz, hp.sky.perm);
     int rc = HVOX_OK;
+    // on failure, wait for the uploads already enqueued before the host tables they read go away
+    auto bail = [&](int r) {
+        (void)hipStreamSynchronize(st);
+        return r;
+    };
     auto chk = [&](hipError_t e, const char *what) {
         if (e != hipSuccess && rc == HVOX_OK) {
             rc = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? HVOX_ERR_OOM : HVOX_ERR_HIP;
@@ -454,7 +528,7 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
     chk(upload(pl, sx, &pl->sky_xyz, st), "sky coordinates");
     chk(upload(pl, hp.vis.perm, &pl->vis_perm, st), "visibility permutation");
     chk(upload(pl, hp.sky.perm, &pl->sky_perm, st), "sky permutation");
-    if (rc) return rc;
+    if (rc) return bail(rc);
 
     // Fourier transforms of the two ES kernels by Gauss-Legendre quadrature:
     // K_hat(nu) = (w/2) sum_q a_q cos(pi nu w z_q), a_q = weight_q ES(z_q).
@@ -511,14 +585,14 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
         chk(upload(pl, tw32, &d, st), "twiddles");
         pl->tw = d;
     }
-    if (rc) return rc;
+    if (rc) return bail(rc);
     if (upload_dir(pl, hp.syn, &pl->syn, st) || upload_dir(pl, hp.ana, &pl->ana, st)) {
         *err = "device allocation of sub-problem tables failed";
-        return HVOX_ERR_OOM;
+        return bail(HVOX_ERR_OOM);
     }
     rc = bin_direction(pl, hp.syn, &pl->syn, pl->sky_xyz, hp.n_pix, st, err);
     if (rc == HVOX_OK) rc = bin_direction(pl, hp.ana, &pl->ana, pl->vis_xyz, hp.n_vis, st, err);
-    if (rc) return rc;
+    if (rc) return bail(rc);
 
     // deconvolution factors of every target, per direction
     double *d_zq = nullptr, *d_aq = nullptr, *d_ctr_v = nullptr, *d_ctr_s = nullptr, *d_hs_v = nullptr,
@@ -534,11 +608,11 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
     chk(upload(pl, cov, &d_cov, st), "chunk ids");
     chk(upload(pl, cos_, &d_cos, st), "chunk ids");
     void *tmp = nullptr;
-    chk(dev_alloc(pl, sizeof(double) * hp.n_vis, &tmp, true), "deconvolution");
+    chk(dev_alloc(pl, sizeof(double) * hp.n_vis, &tmp, true, st), "deconvolution");
     pl->syn.deconv = static_cast<double *>(tmp);
-    chk(dev_alloc(pl, sizeof(double) * hp.n_pix, &tmp, true), "deconvolution");
+    chk(dev_alloc(pl, sizeof(double) * hp.n_pix, &tmp, true, st), "deconvolution");
     pl->ana.deconv = static_cast<double *>(tmp);
-    if (rc) return rc;
+    if (rc) return bail(rc);
     chk(launch_deconv(pl->vis_xyz, hp.n_vis, d_cov, d_ctr_v, d_hs_v, d_zq, d_aq, nq, p.w, pl->syn.deconv, st),
         "deconvolution kernel");
     chk(launch_deconv(pl->sky_xyz, hp.n_pix, d_cos, d_ctr_s, d_hs_s, d_zq, d_aq, nq, p.w, pl->ana.deconv, st),
@@ -546,18 +620,28 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
     // accumulator and workspace
     const size_t delta = p.dtype == HVOX_F64 ? 16 : 8;
     chk(dev_alloc(pl, 16 * static_cast<size_t>(kRowBatch) * static_cast<size_t>(std::max(hp.n_vis, hp.n_pix)), &tmp,
-                  true),
+                  true, st),
         "accumulator");
     pl->acc = static_cast<double *>(tmp);
-    chk(dev_alloc(pl, delta * static_cast<size_t>(hp.ws_elems), &pl->ws, false), "workspace");
+    chk(dev_alloc(pl, delta * static_cast<size_t>(hp.ws_elems), &pl->ws, false, st), "workspace");
     int64_t max_pts = 0;
     for (const DirPlan *dp : {&hp.syn, &hp.ana})
         for (const Batch &b : dp->batches) max_pts = std::max(max_pts, b.pts);
     const size_t staged = p.dtype == HVOX_F64 ? sizeof(StagedSrc<double>) : sizeof(StagedSrc<float>);
-    if (max_pts > 0) chk(dev_alloc(pl, staged * static_cast<size_t>(max_pts), &pl->stage, true), "source staging");
-    if (rc) return rc;
+    if (max_pts > 0) chk(dev_alloc(pl, staged * static_cast<size_t>(max_pts), &pl->stage, true, st), "source staging");
+    if (rc) return bail(rc);
     chk(hipStreamSynchronize(st), "plan upload");
     return rc;
+}
+
+// HVOX_FORCE_OOM_BYTES: fault injection (a plan may not hold more device memory)
+double forced_oom_limit()
+{
+    const char *v = std::getenv("HVOX_FORCE_OOM_BYTES");
+    if (!v || !*v) return -1.0;
+    char *end = nullptr;
+    const double lim = std::strtod(v, &end);
+    return (end != v && lim >= 0.0) ? lim : -1.0;
 }
 
 }  // namespace
@@ -659,13 +743,27 @@ int hvox_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t n_pix
         prm.w = prm.w2 = 3;
         prm.beta = prm.beta2 = 1.0;
     }
+    if ((o.dev_alloc == nullptr) != (o.dev_free == nullptr))
+        return fail(HVOX_ERR_ARG, "dev_alloc and dev_free must be given together");
     auto *pl = new (std::nothrow) hvox_plan_s();
     if (!pl) return fail(HVOX_ERR_OOM, "host allocation failed");
     pl->host_only = (prm.flags & HVOX_PLAN_HOST_ONLY) != 0;
+    pl->alloc_hook = o.dev_alloc;
+    pl->free_hook = o.dev_free;
+    pl->alloc_ctx = o.alloc_ctx;
+    pl->oom_limit = forced_oom_limit();
+    pl->last_stream = static_cast<hipStream_t>(stream);
     std::string err;
     int rc;
     try {
         rc = make_host_plan(uvw, n_vis, xyz, n_pix, prm, o.vis_chunk, o.sky_chunk, &pl->hp, &err);
+        if (rc == HVOX_OK && pl->oom_limit >= 0.0 &&
+            static_cast<double>(device_bytes_bound(pl->hp)) > pl->oom_limit) {
+            // fault injection: a plan whose device memory could exceed the forced limit fails
+            // before touching the device (host-only plans included)
+            rc = HVOX_ERR_OOM;
+            err = "device memory bound of the plan exceeds HVOX_FORCE_OOM_BYTES";
+        }
         if (rc == HVOX_OK && !pl->host_only) rc = build_device(pl, static_cast<hipStream_t>(stream), &err);
     } catch (const std::bad_alloc &) {
         rc = HVOX_ERR_OOM;
@@ -675,11 +773,11 @@ int hvox_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t n_pix
         err = ex.what();
     }
     if (rc != HVOX_OK) {
+        if (!pl->host_only) (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));   // uploads in flight
         release(pl);
         delete pl;
         return fail(rc, err);
     }
-    pl->last_stream = static_cast<hipStream_t>(stream);
     pl->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = pl;
     return HVOX_OK;
@@ -701,6 +799,41 @@ int hvox_analysis(hvox_plan_t plan, const void *vis, void *sky, int32_t ntrans, 
     } catch (...) {
         return fail(HVOX_ERR_HIP, "unexpected failure in hvox_analysis");
     }
+}
+
+int hvox_plan_upload(hvox_plan_t plan, void *stream)
+{
+    if (!plan) return fail(HVOX_ERR_ARG, "NULL plan");
+    if (!plan->host_only) return fail(HVOX_ERR_STATE, "the plan already has its device part");
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    plan->last_stream = st;
+    std::string err;
+    int rc;
+    try {
+        rc = build_device(plan, st, &err);
+    } catch (const std::bad_alloc &) {
+        rc = HVOX_ERR_OOM;
+        err = "host allocation failed";
+    } catch (...) {
+        rc = HVOX_ERR_HIP;
+        err = "unexpected failure in hvox_plan_upload";
+    }
+    if (rc != HVOX_OK) {
+        (void)hipStreamSynchronize(st);
+        release(plan);
+        plan->vis_xyz = plan->sky_xyz = nullptr;
+        plan->vis_perm = plan->sky_perm = nullptr;
+        plan->precor = plan->tw = plan->ws = plan->stage = nullptr;
+        plan->acc = nullptr;
+        plan->syn = DevDir{};
+        plan->ana = DevDir{};
+        return fail(rc, err);
+    }
+    plan->host_only = false;
+    plan->hp.prm.flags &= ~HVOX_PLAN_HOST_ONLY;
+    plan->plan_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return HVOX_OK;
 }
 
 int hvox_free(hvox_plan_t plan)
@@ -738,11 +871,8 @@ int hvox_plan_info(hvox_plan_t plan, hvox_plan_info_t *out)
     out->workspace_bytes = hp.ws_elems * delta;
     out->max_pair_workspace_bytes = hp.max_pair_ws * delta;
     if (plan->host_only) {
-        int64_t r = 16 * (hp.n_vis + hp.n_pix) + 4 * (hp.n_vis + hp.n_pix) + 8 * (hp.n_vis + hp.n_pix) +
-                    16 * kRowBatch * std::max(hp.n_vis, hp.n_pix);
-        r += static_cast<int64_t>((hp.syn.pairs.size() + hp.ana.pairs.size()) * sizeof(PairDev));
-        r += static_cast<int64_t>((hp.syn.direct.size() + hp.ana.direct.size()) * sizeof(DirectItem));
-        out->resident_bytes = r;
+        // bound of what hvox_plan_upload allocates besides the workspace
+        out->resident_bytes = device_bytes_bound(hp) - hp.ws_elems * delta;
     } else {
         out->resident_bytes = static_cast<int64_t>(plan->resident_bytes);
     }
@@ -750,6 +880,10 @@ int hvox_plan_info(hvox_plan_t plan, hvox_plan_info_t *out)
     out->direct_terms = hp.syn.direct_terms;
     out->est_seconds = hp.syn.est_seconds + hp.ana.est_seconds;
     out->plan_seconds = plan->plan_seconds;
+    out->device_bytes = plan->host_only ? device_bytes_bound(hp) : static_cast<int64_t>(plan->device_bytes);
+    out->flags = hp.prm.flags;
+    out->on_device = plan->host_only ? 0 : 1;
+    out->n_direct_layers = static_cast<int64_t>(std::max<size_t>(hp.syn.direct_layer_off.size(), 1) - 1);
     return HVOX_OK;
 }
 

@@ -170,6 +170,11 @@ struct DirPlan {                         // one direction (synthesis or analysis
     int64_t tiles_total = 0;             // spreading tiles over all batches
     std::vector<SpreadTile> spread_tiles;   // spreading tiles of every batch (built with the binning)
     std::vector<DirectItem> direct;
+    // direct items in launch order: [direct_layer_off[l], direct_layer_off[l + 1]) is launch l.
+    // One launch of every item unless the plan is deterministic: then layer l holds the l-th
+    // source segment of every target tile, so the items of a launch never share a target and
+    // add into the accumulator without atomics, layer after layer.
+    std::vector<int64_t> direct_layer_off;
     double grid_cells = 0.0, direct_terms = 0.0;
     double est_seconds = 0.0;
     double alg_bytes[HVOX_K_COUNT] = {0};
@@ -195,6 +200,7 @@ struct Params {
     double alpha = 1.0;
     double ws_cap = 4.0 * 1024 * 1024 * 1024;
     int flags = 0;
+    bool deterministic() const { return (flags & HVOX_DETERMINISTIC) != 0; }
 };
 
 struct HostPlan {
@@ -225,6 +231,11 @@ int make_host_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t 
                    const Params &prm, const int32_t *vis_chunk, const int32_t *sky_chunk,
                    HostPlan *hp, std::string *err);
 int32_t smooth_even(int64_t n);
+// upper bound of the device bytes of a plan (resident tables + workspace), from the host plan
+int64_t device_bytes_bound(const HostPlan &hp);
+// complex elements a single sub-problem region may hold: kernels index within one
+// region in 32-bit arithmetic
+constexpr int64_t kMaxRegionElems = (int64_t(1) << 31) - 1;
 int factor_radices(int32_t n, uint8_t *radix);
 void gauss_legendre(int n, std::vector<double> *x, std::vector<double> *w);
 

@@ -202,7 +202,7 @@ __global__ void k_prephase(const PairDev *__restrict__ pairs, const int64_t *__r
     double ph = 0.0;
     for (int d = 0; d < 3; ++d) ph += P.sc[d] * xp[d];
     const double2 e = cis_cycles(ph, iota);
-    const cplx<T> c = in[perm[n]];
+    const cplx<T> c = in[perm ? perm[n] : n];   // no permutation: data already in chunk order
     StagedSrc<T> s;
     s.v[0] = T(c.x * e.x - c.y * e.y);
     s.v[1] = T(c.x * e.y + c.y * e.x);
@@ -662,7 +662,7 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
                                                 int npairs, int64_t block0, const double *__restrict__ xyz,
                                                 int64_t ntgt, const double *__restrict__ deconv,
                                                 const cplx<T> *__restrict__ ws, double *__restrict__ acc, int w,
-                                                T beta, double iota)
+                                                T beta, double iota, int det)
 {
     __shared__ T ker[kInterpTargets][3 * kWMax];
     const int sub = threadIdx.x & (kInterpLanes - 1), slot = threadIdx.x / kInterpLanes;
@@ -731,14 +731,21 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
         ai += __shfl_xor(ai, off, 64);
     }
     if (active && sub == 0) {
+        // post-phase exp(2 pi i iota s_k.x_c) in float64 in both precisions
         double ph = 0.0;
         for (int d = 0; d < 3; ++d) ph += s_k[d] * P.xc[d];
-        T er, ei;
+        double er, ei;
         cis_rev(iota * ph, er, ei);
         const double dk = deconv[k];
         const double vr = (double)ar * dk, vi = (double)ai * dk;
-        atomicAdd(acc + 2 * k, vr * (double)er - vi * (double)ei);
-        atomicAdd(acc + 2 * k + 1, vr * (double)ei + vi * (double)er);
+        if (det) {
+            // deterministic plans: no other workgroup of this launch adds into target k
+            acc[2 * k] += vr * er - vi * ei;
+            acc[2 * k + 1] += vr * ei + vi * er;
+        } else {
+            atomicAdd(acc + 2 * k, vr * er - vi * ei);
+            atomicAdd(acc + 2 * k + 1, vr * ei + vi * er);
+        }
     }
 }
 
@@ -765,7 +772,8 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__r
                                                            const double *__restrict__ txyz, int64_t ntgt,
                                                            const int32_t *__restrict__ perm,
                                                            const cplx<T> *__restrict__ in, int64_t in_stride,
-                                                           double *__restrict__ acc, int64_t acc_stride, double iota)
+                                                           double *__restrict__ acc, int64_t acc_stride, double iota,
+                                                           int det)
 {
     static_assert(kDirectSrcTile == kDirectThreads && kDirectTile == 2 * kDirectThreads, "direct tiling");
     __shared__ double lx[kDirectSrcTile], ly[kDirectSrcTile], lz[kDirectSrcTile];
@@ -804,13 +812,13 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__r
             lx[tid] = dxv[0];
             ly[tid] = dxv[1];
             lz[tid] = dxv[2];
-            T ec, es;
-            cis_rev(iota * ph, ec, es);   // exp(2 pi i iota ph): float64 reduction, plan-precision sine / cosine
-            const int64_t u = perm[n];
+            double ec, es;
+            cis_rev(iota * ph, ec, es);   // exp(2 pi i iota ph), float64
+            const int64_t u = perm ? perm[n] : n;
 #pragma unroll
             for (int r = 0; r < NT; ++r) {
                 const cplx<T> c = in[r * in_stride + u];
-                lc[r][tid] = mk<T>(c.x * ec - c.y * es, c.x * es + c.y * ec);
+                lc[r][tid] = mk<T>(T(c.x * ec - c.y * es), T(c.x * es + c.y * ec));
             }
         }
         __syncthreads();
@@ -840,7 +848,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__r
             ph0 += sk0[d] * xS[d];
             ph1 += sk1[d] * xS[d];
         }
-        T e0c, e0s, e1c, e1s;
+        double e0c, e0s, e1c, e1s;   // tile reference phases, float64
         cis_rev(iota * ph0, e0c, e0s);
         cis_rev(iota * ph1, e1c, e1s);
         const double2 e0 = make_double2(e0c, e0s), e1 = make_double2(e1c, e1s);
@@ -855,13 +863,19 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__r
 #pragma unroll
     for (int r = 0; r < NT; ++r) {
         double *ar = acc + r * acc_stride;
-        if (has0) {
-            atomicAdd(ar + 2 * k0, a0r[r]);
-            atomicAdd(ar + 2 * k0 + 1, a0i[r]);
-        }
-        if (has1) {
-            atomicAdd(ar + 2 * k1, a1r[r]);
-            atomicAdd(ar + 2 * k1 + 1, a1i[r]);
+        if (det) {
+            // deterministic plans launch items sharing no target together (one layer)
+            if (has0) { ar[2 * k0] += a0r[r]; ar[2 * k0 + 1] += a0i[r]; }
+            if (has1) { ar[2 * k1] += a1r[r]; ar[2 * k1 + 1] += a1i[r]; }
+        } else {
+            if (has0) {
+                atomicAdd(ar + 2 * k0, a0r[r]);
+                atomicAdd(ar + 2 * k0 + 1, a0i[r]);
+            }
+            if (has1) {
+                atomicAdd(ar + 2 * k1, a1r[r]);
+                atomicAdd(ar + 2 * k1 + 1, a1i[r]);
+            }
         }
     }
 }
@@ -876,7 +890,7 @@ __global__ void k_finalize(const double *__restrict__ acc, int64_t n, const int3
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    out[perm[k]] = mk<T>(T(acc[2 * k]), real_only ? T(0) : T(acc[2 * k + 1]));
+    out[perm ? perm[k] : k] = mk<T>(T(acc[2 * k]), real_only ? T(0) : T(acc[2 * k + 1]));
 }
 
 // ---------------------------------------------------------------------------
@@ -973,12 +987,12 @@ hipError_t launch_transpose(const PairDev *pairs, const int64_t *prefix, int npa
 template <typename T>
 hipError_t launch_interp(const PairDev *pairs, const int64_t *bprefix, int npairs, int64_t blocks, const double *xyz,
                          int64_t ntgt, const double *deconv, const void *ws, double *acc, int w, double beta,
-                         double iota, hipStream_t st)
+                         double iota, int det, hipStream_t st)
 {
     for (int64_t b0 = 0; b0 < blocks; b0 += kMaxLaunchBlocks) {
         const int64_t nb = std::min<int64_t>(kMaxLaunchBlocks, blocks - b0);
         hipLaunchKernelGGL(k_interp<T>, dim3(static_cast<unsigned>(nb)), dim3(256), 0, st, pairs, bprefix, npairs, b0,
-                           xyz, ntgt, deconv, static_cast<const cplx<T> *>(ws), acc, w, T(beta), iota);
+                           xyz, ntgt, deconv, static_cast<const cplx<T> *>(ws), acc, w, T(beta), iota, det);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -988,7 +1002,8 @@ hipError_t launch_interp(const PairDev *pairs, const int64_t *bprefix, int npair
 template <typename T, int NT>
 static hipError_t launch_direct_rows(const DirectItem *items, int64_t nitems, const double *sxyz, int64_t nsrc,
                                      const double *txyz, int64_t ntgt, const int32_t *perm, const void *in,
-                                     int64_t in_stride, double *acc, int64_t acc_stride, double iota, hipStream_t st)
+                                     int64_t in_stride, double *acc, int64_t acc_stride, double iota, int det,
+                                     hipStream_t st)
 {
     // one workgroup per item, in launches of at most kMaxLaunchBlocks workgroups
     // (a dispatch counts its work-items in 32 bits)
@@ -996,7 +1011,7 @@ static hipError_t launch_direct_rows(const DirectItem *items, int64_t nitems, co
         const int64_t nb = std::min<int64_t>(kMaxLaunchBlocks, nitems - i0);
         hipLaunchKernelGGL((k_direct<T, NT>), dim3(static_cast<unsigned>(nb)), dim3(kDirectThreads), 0, st,
                            items + i0, sxyz, nsrc, txyz, ntgt, perm, static_cast<const cplx<T> *>(in), in_stride, acc,
-                           acc_stride, iota);
+                           acc_stride, iota, det);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1006,18 +1021,18 @@ static hipError_t launch_direct_rows(const DirectItem *items, int64_t nitems, co
 template <typename T>
 hipError_t launch_direct(const DirectItem *items, int64_t nitems, const double *sxyz, int64_t nsrc,
                          const double *txyz, int64_t ntgt, const int32_t *perm, const void *in, int64_t in_stride,
-                         double *acc, int64_t acc_stride, int rows, double iota, hipStream_t st)
+                         double *acc, int64_t acc_stride, int rows, double iota, int det, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
     switch (rows) {
     case 1: return launch_direct_rows<T, 1>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
-                                            acc_stride, iota, st);
+                                            acc_stride, iota, det, st);
     case 2: return launch_direct_rows<T, 2>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
-                                            acc_stride, iota, st);
+                                            acc_stride, iota, det, st);
     case 3: return launch_direct_rows<T, 3>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
-                                            acc_stride, iota, st);
+                                            acc_stride, iota, det, st);
     case 4: return launch_direct_rows<T, 4>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
-                                            acc_stride, iota, st);
+                                            acc_stride, iota, det, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1047,14 +1062,15 @@ template hipError_t launch_fft<double>(const PairDev *, const int64_t *, int, in
 template hipError_t launch_transpose<float>(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
 template hipError_t launch_transpose<double>(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
 template hipError_t launch_interp<float>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
-                                         const double *, const void *, double *, int, double, double, hipStream_t);
+                                         const double *, const void *, double *, int, double, double, int, hipStream_t);
 template hipError_t launch_interp<double>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
-                                          const double *, const void *, double *, int, double, double, hipStream_t);
+                                          const double *, const void *, double *, int, double, double, int,
+                                          hipStream_t);
 template hipError_t launch_direct<float>(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
-                                         const int32_t *, const void *, int64_t, double *, int64_t, int, double,
+                                         const int32_t *, const void *, int64_t, double *, int64_t, int, double, int,
                                          hipStream_t);
 template hipError_t launch_direct<double>(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
-                                          const int32_t *, const void *, int64_t, double *, int64_t, int, double,
+                                          const int32_t *, const void *, int64_t, double *, int64_t, int, double, int,
                                           hipStream_t);
 template hipError_t launch_finalize<float>(const double *, int64_t, const int32_t *, void *, int, hipStream_t);
 template hipError_t launch_finalize<double>(const double *, int64_t, const int32_t *, void *, int, hipStream_t);

@@ -452,6 +452,8 @@ PairGeom pair_geometry(const double X[3], const double S[3], const Params &p)
     g.dz = wx * wy * wz;
     g.bufA = std::max(g.bx, g.dz);
     g.bufB = std::max(g.bx, g.cy);
+    // the kernels index inside one grid region with 32-bit arithmetic
+    if (g.g1 > kMaxRegionElems || g.bufA > kMaxRegionElems || g.bufB > kMaxRegionElems) g.fits = false;
     return g;
 }
 
@@ -594,9 +596,13 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
         }
         if (items >= kDirectMinItems) break;
     }
-    for (const Group &g : groups)
+    // layer of an item: its source segment's position in its group's list (deterministic plans
+    // launch layer by layer; other plans launch every item at once)
+    std::vector<int64_t> layer_of;
+    for (const Group &g : groups) {
+        int64_t layer = 0;
         for (const auto &r : g.ranges)
-            for (int64_t s0 = r.first; s0 < r.second; s0 += seg)
+            for (int64_t s0 = r.first; s0 < r.second; s0 += seg, ++layer)
                 for (int64_t t0 = g.t0; t0 < g.t1; t0 += kDirectTile) {
                     DirectItem it;
                     it.tgt_off = t0;
@@ -604,9 +610,33 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
                     it.tgt_cnt = static_cast<int32_t>(std::min<int64_t>(kDirectTile, g.t1 - t0));
                     it.src_cnt = static_cast<int32_t>(std::min<int64_t>(seg, r.second - s0));
                     dp->direct.push_back(it);
+                    layer_of.push_back(layer);
                 }
+    }
+    dp->direct_layer_off.assign(1, 0);
+    if (p.deterministic() && !dp->direct.empty()) {
+        const int64_t nl = *std::max_element(layer_of.begin(), layer_of.end()) + 1;
+        std::vector<int64_t> cnt(nl + 1, 0);
+        for (int64_t l : layer_of) cnt[l + 1]++;
+        for (int64_t l = 0; l < nl; ++l) cnt[l + 1] += cnt[l];
+        std::vector<DirectItem> sorted(dp->direct.size());
+        std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+        for (size_t q = 0; q < dp->direct.size(); ++q) sorted[pos[layer_of[q]]++] = dp->direct[q];
+        dp->direct.swap(sorted);
+        dp->direct_layer_off.assign(cnt.begin() + 1, cnt.end());
+        dp->direct_layer_off.insert(dp->direct_layer_off.begin(), 0);
+    } else if (!dp->direct.empty()) {
+        dp->direct_layer_off.push_back(static_cast<int64_t>(dp->direct.size()));
+    }
     dp->alg_flops[HVOX_K_DIRECT] = dp->direct_terms;
 
+    // Deterministic plans: sub-problems source-chunk-major, and a batch never holds two
+    // sub-problems of one target chunk, so the interpolation of a batch adds into every
+    // target at most once (plain read-modify-write, no atomics) and the batches add in order.
+    if (p.deterministic())
+        std::stable_sort(nufft.begin(), nufft.end(), [](const Cand &a, const Cand &b) {
+            return a.i != b.i ? a.i < b.i : a.j < b.j;
+        });
     // group NUFFT sub-problems into batches sharing the workspace
     dp->pairs.clear();
     dp->batches.clear();
@@ -628,10 +658,16 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
         b.pair0 = static_cast<int64_t>(dp->pairs.size());
         int64_t sumG = 0, sumA = 0, sumB = 0, npts = 0;
         size_t k1 = k;
+        std::vector<uint8_t> tgt_seen;          // deterministic plans: target chunks of this batch
+        if (p.deterministic()) tgt_seen.assign(static_cast<size_t>(tgt.nc), 0);
         while (k1 < nufft.size()) {
             const int64_t gg = nufft[k1].g.g1, a = nufft[k1].g.bufA, bb = nufft[k1].g.bufB;
             const int64_t np = src.off[nufft[k1].i + 1] - src.off[nufft[k1].i];
             if (k1 > k && (sumG + sumA + sumB + gg + a + bb > cap || npts + np > kMaxBatchPts)) break;
+            if (p.deterministic()) {
+                if (tgt_seen[nufft[k1].j]) break;
+                tgt_seen[nufft[k1].j] = 1;
+            }
             npts += np;
             sumG += gg;
             sumA += a;
@@ -742,6 +778,47 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
 }
 
 }  // namespace
+
+// Upper bound of the device memory a plan allocates (tables, workspace, staging,
+// accumulator, and the binning temporaries of plan creation).  Exact but for
+// the tile lists: a source is counted under every tile its footprint can reach
+// (ceil((w - 1) / tile) + 1 tiles per dimension), and every crowded tile part
+// is counted as if each took a full descriptor.
+int64_t device_bytes_bound(const HostPlan &hp)
+{
+    const Params &p = hp.prm;
+    const int64_t nv = hp.n_vis, np = hp.n_pix;
+    const int64_t delta = p.dtype == HVOX_F64 ? 16 : 8;
+    const int64_t prec = p.dtype == HVOX_F64 ? 8 : 4;
+    const int64_t staged = p.dtype == HVOX_F64 ? sizeof(StagedSrc<double>) : sizeof(StagedSrc<float>);
+    int64_t b = 24 * (nv + np) + 4 * (nv + np) + 8 * (nv + np) + 4 * (nv + np);   // coords, perms, deconv, chunk ids
+    b += 16 * static_cast<int64_t>(kRowBatch) * std::max(nv, np);                // accumulator
+    b += prec * static_cast<int64_t>(hp.precor_nu.size()) + delta * hp.tw_total;
+    const int nq = 2 * std::max(p.w, p.w2) + 60;
+    b += 16 * nq + 48 * (static_cast<int64_t>(hp.vis.nc) + hp.sky.nc);          // quadrature, centres, scales
+    const int per_dim[3] = {(p.w - 1 + kTileX - 1) / kTileX + 1, (p.w - 1 + kTileY - 1) / kTileY + 1,
+                            (p.w - 1 + kTileZ - 1) / kTileZ + 1};
+    const int64_t touch = static_cast<int64_t>(per_dim[0]) * per_dim[1] * per_dim[2];
+    int64_t max_pts = 0, temp = 0;
+    for (const DirPlan *dp : {&hp.syn, &hp.ana}) {
+        b += static_cast<int64_t>(dp->pairs.size() * sizeof(PairDev));
+        b += static_cast<int64_t>(dp->direct.size() * sizeof(DirectItem));
+        b += 8 * static_cast<int64_t>(dp->pre_pts.size() + dp->pre_tgts.size() + dp->pre_ttiles.size() +
+                                      dp->pre_tiles[0].size() + dp->pre_tiles[1].size() + dp->pre_tiles[2].size());
+        int64_t pts = 0;
+        for (const Batch &bt : dp->batches) {
+            pts += bt.pts;
+            max_pts = std::max(max_pts, bt.pts);
+        }
+        const int64_t records = touch * pts;
+        b += 4 * std::max<int64_t>(records, 1);
+        b += static_cast<int64_t>(sizeof(SpreadTile)) * (dp->tiles_total + records / kSpreadSplit + 1);
+        temp = std::max(temp, 12 * dp->tiles_total);                            // binning counts + cursors
+    }
+    b += staged * max_pts;
+    b += delta * hp.ws_elems;
+    return b + temp;
+}
 
 int make_host_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t n_pix,
                    const Params &prm_in, const int32_t *vis_chunk, const int32_t *sky_chunk,

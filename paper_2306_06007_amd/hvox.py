@@ -21,6 +21,8 @@ HVOX_F64 = 1
 HVOX_REAL_SKY = 0x1
 HVOX_PLAN_HOST_ONLY = 0x2
 HVOX_TIMING = 0x4
+HVOX_PREORDERED = 0x8
+HVOX_DETERMINISTIC = 0x10
 
 KERNELS = ("zero", "spread", "fft_x", "fft_y", "fft_z", "interp", "direct", "finalize", "transpose", "prephase")
 
@@ -34,6 +36,11 @@ class HvoxError(RuntimeError):
         self.code = code
 
 
+# device-memory hooks of hvox_opts: dev_alloc(bytes, ctx, stream) -> ptr, dev_free(ptr, bytes, ctx, stream)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class HvoxOpts(ctypes.Structure):
     _fields_ = [("max_fft_bytes", ctypes.c_double),
                 ("anisotropy", ctypes.c_double),
@@ -44,7 +51,10 @@ class HvoxOpts(ctypes.Structure):
                 ("vis_chunk", ctypes.POINTER(ctypes.c_int32)),
                 ("sky_chunk", ctypes.POINTER(ctypes.c_int32)),
                 ("flags", ctypes.c_int32),
-                ("ntrans_hint", ctypes.c_int32)]
+                ("ntrans_hint", ctypes.c_int32),
+                ("dev_alloc", ALLOC_FN),
+                ("dev_free", FREE_FN),
+                ("alloc_ctx", ctypes.c_void_p)]
 
 
 class HvoxPlanInfo(ctypes.Structure):
@@ -61,7 +71,9 @@ class HvoxPlanInfo(ctypes.Structure):
                 ("resident_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("max_pair_workspace_bytes", ctypes.c_int64),
                 ("grid_cells", ctypes.c_double), ("direct_terms", ctypes.c_double),
-                ("est_seconds", ctypes.c_double), ("plan_seconds", ctypes.c_double)]
+                ("est_seconds", ctypes.c_double), ("plan_seconds", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64), ("flags", ctypes.c_int32), ("on_device", ctypes.c_int32),
+                ("n_direct_layers", ctypes.c_int64)]
 
 
 class HvoxStats(ctypes.Structure):
@@ -69,7 +81,7 @@ class HvoxStats(ctypes.Structure):
                 ("alg_bytes", ctypes.c_double * len(KERNELS)), ("alg_flops", ctypes.c_double * len(KERNELS))]
 
 
-EXPORTS = ("hvox_plan", "hvox_synthesis", "hvox_analysis", "hvox_free", "hvox_plan_info",
+EXPORTS = ("hvox_plan", "hvox_plan_upload", "hvox_synthesis", "hvox_analysis", "hvox_free", "hvox_plan_info",
            "hvox_plan_permutation", "hvox_plan_chunks", "hvox_stats", "hvox_stats_reset", "hvox_set_timing",
            "hvox_kernel_params", "hvox_alg1", "hvox_partition", "hvox_error_string",
            "hvox_last_error", "hvox_version")
@@ -96,6 +108,8 @@ def load_library():
         f = getattr(lib, name)
         f.restype = ctypes.c_int
         f.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
+    lib.hvox_plan_upload.restype = ctypes.c_int
+    lib.hvox_plan_upload.argtypes = [vp, vp]
     lib.hvox_free.restype = ctypes.c_int
     lib.hvox_free.argtypes = [vp]
     lib.hvox_plan_info.restype = ctypes.c_int
@@ -183,6 +197,30 @@ def _torch():
     return torch
 
 
+def _torch_alloc(nbytes, ctx, stream):
+    """dev_alloc hook: a block from PyTorch's caching allocator on the current
+    device, associated with ``stream`` (NULL on failure: the plan call then
+    reports HVOX_ERR_OOM)."""
+    torch = _torch()
+    try:
+        return int(torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                      int(stream or 0) or None))
+    except Exception:
+        return None
+
+
+def _torch_free(ptr, nbytes, ctx, stream):
+    try:
+        _torch().cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+# kept alive for the life of the process (the library may call them from any plan)
+TORCH_ALLOC = ALLOC_FN(_torch_alloc)
+TORCH_FREE = FREE_FN(_torch_free)
+
+
 class Plan:
     """A planned HVOX operator for fixed baselines ``uvw`` (n_vis, 3) [wavelengths]
     and sky points ``xyz`` (n_pix, 3).
@@ -196,7 +234,9 @@ class Plan:
                  anisotropy: float = 0.0, upsampfac: float = 0.0, inner_upsampfac: float = 0.0,
                  direct_threshold: float = -1.0,
                  workspace_bytes: float = 0.0, vis_chunk=None, sky_chunk=None, real_sky: bool = False,
-                 host_only: bool = False, timing: bool = False, ntrans_hint: int = 1, stream=None):
+                 host_only: bool = False, timing: bool = False, ntrans_hint: int = 1, stream=None,
+                 preordered: bool = False, deterministic: bool = False, allocator: Optional[str] = "torch",
+                 alloc_hooks=None):
         self._lib = load_library()
         self._plan = ctypes.c_void_p(None)
         uvw = _coords(uvw, "uvw")
@@ -228,8 +268,20 @@ class Plan:
             keep.append(sc)
             opts.sky_chunk = sc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         opts.flags = ((HVOX_REAL_SKY if real_sky else 0) | (HVOX_PLAN_HOST_ONLY if host_only else 0) |
-                      (HVOX_TIMING if timing else 0))
+                      (HVOX_TIMING if timing else 0) | (HVOX_PREORDERED if preordered else 0) |
+                      (HVOX_DETERMINISTIC if deterministic else 0))
+        # device memory: PyTorch's caching allocator (default), the library's own
+        # hipMalloc (allocator=None), or caller hooks (alloc_hooks=(ALLOC_FN, FREE_FN, ctx))
+        if alloc_hooks is not None:
+            opts.dev_alloc, opts.dev_free, opts.alloc_ctx = alloc_hooks
+            self._hooks = alloc_hooks
+        elif allocator == "torch":
+            opts.dev_alloc, opts.dev_free = TORCH_ALLOC, TORCH_FREE
+        elif allocator is not None:
+            raise ValueError("allocator must be 'torch' or None")
         self.real_sky = real_sky
+        self.preordered = preordered
+        self.deterministic = deterministic
         st = None
         if not host_only:
             torch = _torch()
@@ -302,6 +354,17 @@ class Plan:
                                        x.shape[0], ctypes.c_void_p(self._stream_handle(stream))))
         return y[0] if squeeze and out is None else y
 
+    def upload(self, stream=None):
+        """Create the device part of a host-only plan (hvox_plan_upload)."""
+        if self._plan.value is None:
+            raise HvoxError(-5, "plan freed")
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("HVOX plans need a ROCm GPU")
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        _check(self._lib.hvox_plan_upload(self._plan, ctypes.c_void_p(self._stream_handle(stream))))
+        self.host_only = False
+
     def info(self) -> dict:
         inf = HvoxPlanInfo()
         _check(self._lib.hvox_plan_info(self._plan, ctypes.byref(inf)))
@@ -355,20 +418,6 @@ class Plan:
         return False
 
 
-def footprint_bound(n_vis: int, n_pix: int, dtype: str, workspace_bytes: float) -> float:
-    """Device memory of a plan estimated before planning: coordinates,
-    permutations, deconvolution factors and accumulator per point (the
-    accumulator holds four rows, the direct sum's row batch), the workspace
-    cap, and 64 MB for the sub-problem tables.  It bounds plans whose NUFFT
-    sub-problems stay small (the serving workload's); a plan that sends many
-    sources through NUFFT grids also holds their staged records (32 / 64 bytes
-    per source of its largest batch) and tile lists (4 bytes per source and
-    grid-1 tile it touches), which can exceed the 64 MB: its plan_info()
-    reports the exact resident bytes."""
-    per_point = 24 + 4 + 8 + 16
-    return float(per_point * (n_vis + n_pix) + 16 * 4 * max(n_vis, n_pix) + workspace_bytes + 64e6)
-
-
 def rel_l2(y, ref) -> float:
     y = np.asarray(y)
     ref = np.asarray(ref)
@@ -378,4 +427,4 @@ def rel_l2(y, ref) -> float:
 
 
 __all__ = ["Plan", "HvoxError", "load_library", "kernel_params", "alg1", "partition", "EXPORTS",
-           "footprint_bound", "rel_l2", "KERNELS"]
+           "rel_l2", "KERNELS"]

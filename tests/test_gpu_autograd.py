@@ -45,8 +45,13 @@ def test_gradient_vs_oracle_adjoint(dtype, eps):
         L.backward()
         g = x.grad.double().cpu().numpy()
         r = (V.detach() - yt).cpu().numpy().astype(np.complex128)
-    g_ref = oracle.analysis(wl.uvw, wl.xyz, r).real[0]
-    assert oracle.rel_l2(g, g_ref) <= 2 * eps
+    gc = oracle.analysis(wl.uvw, wl.xyz, r)[0]
+    g_ref = gc.real
+    # the analysis kernel meets eps on the complex A^H r; its real part carries
+    # at most that error over the smaller norm ||Re A^H r||
+    bound = eps * np.linalg.norm(gc) / np.linalg.norm(g_ref)
+    print(f"[gradient {dtype}] rel-l2 {oracle.rel_l2(g, g_ref):.3e} bound {bound:.3e}", flush=True)
+    assert oracle.rel_l2(g, g_ref) <= bound
 
 
 def test_gradient_central_differences():
@@ -122,7 +127,9 @@ def test_gradient_full_size_sampled():
             # and, as measured, to 1e-3 of the directional derivative itself
             assert abs(fd - g @ d) <= 1e-3 * abs(g @ d) + 1e-6 * gn, (k, fd, g @ d, gn)
     rp = W.sample_rows(wl.n_pix, 4096, seed=61)
-    g_ref = oracle.analysis(wl.uvw, wl.xyz, r[None], rows=rp).real[0]
+    gc = oracle.analysis(wl.uvw, wl.xyz, r[None], rows=rp)[0]
+    g_ref = gc.real
     err = oracle.rel_l2(g[rp], g_ref)
-    print(f"[full-size gradient] sampled rel-l2 vs oracle adjoint {err:.3e}", flush=True)
-    assert err <= 2 * eps
+    bound = eps * np.linalg.norm(gc) / np.linalg.norm(g_ref)     # eps on A^H r, over ||Re A^H r||
+    print(f"[full-size gradient] sampled rel-l2 vs oracle adjoint {err:.3e} (bound {bound:.3e})", flush=True)
+    assert err <= bound

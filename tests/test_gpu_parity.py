@@ -35,8 +35,21 @@ def _np(t):
     return t.detach().cpu().numpy().astype(np.complex128)
 
 
-def both_directions(uvw, xyz, sky, vis, eps, dtype, rows_vis=None, rows_pix=None, **kw):
-    """Run synthesis and analysis on the GPU; return (err_syn, err_ana, plan info)."""
+# Element-wise bar (the max-abs error relative to max |y_ref|, besides the
+# relative l2 error <= eps): every single output within C_ELEM * eps of the
+# oracle, relative to the largest reference output.  Errors of chunked type-3
+# evaluation are not uniform over the targets (those near the corners of a
+# sub-problem box, recovered from the most strongly deconvolved modes, carry the
+# largest); C_ELEM bounds how far the worst one may stand above the l2 average.
+C_ELEM = 4.0
+ELEM_LOG = []      # (tag, rel-l2 syn, rel-l2 ana, max syn, max ana) of every case, printed at the end
+
+
+def both_directions(uvw, xyz, sky, vis, eps, dtype, rows_vis=None, rows_pix=None, elem_bound=None, **kw):
+    """Run synthesis and analysis on the GPU; return (err_syn, err_ana, plan
+    info) as relative l2 errors against the oracle, after asserting the
+    element-wise bar (C_ELEM * eps unless elem_bound is given; eps = 0 and
+    elem_bound = 0 skip it)."""
     with hv.Plan(uvw, xyz, eps, dtype, **kw) as p:
         V = _np(p.synthesis(_t(sky, dtype)))
         I = _np(p.analysis(_t(vis, dtype)))
@@ -47,7 +60,17 @@ def both_directions(uvw, xyz, sky, vis, eps, dtype, rows_vis=None, rows_pix=None
         V = V[..., rows_vis]
     if rows_pix is not None:
         I = I[..., rows_pix]
-    return oracle.rel_l2(V.reshape(Vref.shape), Vref), oracle.rel_l2(I.reshape(Iref.shape), Iref), info
+    V = V.reshape(Vref.shape)
+    I = I.reshape(Iref.shape)
+    es, ea = oracle.rel_l2(V, Vref), oracle.rel_l2(I, Iref)
+    ms, ma = oracle.max_rel_err(V, Vref), oracle.max_rel_err(I, Iref)
+    ELEM_LOG.append((f"{dtype} eps={eps:g}", es, ea, ms, ma))
+    print(f"  element-wise: syn max {ms:.3e} ({ms / max(es, 1e-300):.2f}x l2), "
+          f"ana max {ma:.3e} ({ma / max(ea, 1e-300):.2f}x l2)", flush=True)
+    bound = C_ELEM * eps if elem_bound is None else elem_bound
+    if bound > 0:
+        assert ms <= bound and ma <= bound, (ms, ma, bound)
+    return es, ea, info
 
 
 def _report(tag, es, ea, info):
@@ -70,7 +93,8 @@ def test_compact_disk_monolithic_nufft(dtype, eps):
 def test_compact_disk_all_direct(dtype, tol):
     wl = W.compact_disk()
     eps = 0.0 if dtype == "f64" else 1e-4
-    es, ea, info = both_directions(wl.uvw, wl.xyz, wl.sky, wl.vis, eps, dtype, direct_threshold=math.inf)
+    es, ea, info = both_directions(wl.uvw, wl.xyz, wl.sky, wl.vis, eps, dtype, direct_threshold=math.inf,
+                                   elem_bound=C_ELEM * tol)
     _report(f"direct {dtype}", es, ea, info)
     assert info["n_pairs_nufft"] == 0
     assert es <= tol and ea <= tol
@@ -289,11 +313,12 @@ def test_crowded_tiles(dtype, eps, budget):
 
 # ---- full-size SKA-like workload (995k x 1M), sampled rows -------------------------------
 @pytest.mark.slow
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
 def test_ska_like_full_size_sampled(dtype, eps):
     wl = W.ska_like()
-    rv = W.sample_rows(wl.n_vis, 192, seed=21)
-    rp = W.sample_rows(wl.n_pix, 192, seed=22)
+    rv = W.sample_rows(wl.n_vis, 4096, seed=21)
+    rp = W.sample_rows(wl.n_pix, 4096, seed=22)
     es, ea, info = both_directions(wl.uvw, wl.xyz, wl.sky, wl.vis, eps, dtype, rows_vis=rv, rows_pix=rp)
     _report(f"ska-like full {dtype} {eps:g}", es, ea, info)
     assert es <= eps and ea <= eps
@@ -306,11 +331,12 @@ def lofar_like():
 
 
 @pytest.mark.slow
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
 def test_lofar_like_full_size_sampled(lofar_like, dtype, eps):
     wl = lofar_like
-    rv = W.sample_rows(wl.n_vis, 256, seed=31)
-    rp = W.sample_rows(wl.n_pix, 256, seed=32)
+    rv = W.sample_rows(wl.n_vis, 4096, seed=31)
+    rp = W.sample_rows(wl.n_pix, 4096, seed=32)
     es, ea, info = both_directions(wl.uvw, wl.xyz, wl.sky, wl.vis, eps, dtype, rows_vis=rv, rows_pix=rp)
     _report(f"lofar-like full {dtype} {eps:g}", es, ea, info)
     assert info["n_vis_chunks"] > 1 and info["n_sky_chunks"] > 1   # chunked evaluation
@@ -341,3 +367,11 @@ def test_dense_dcos_forced_nufft_sampled():
     _report("dense 1 km forced nufft f32", es, ea, info)
     assert info["n_pairs_direct"] == 0
     assert es <= 1e-4 and ea <= 1e-4
+
+
+def test_zz_element_wise_summary():
+    """Print the element-wise errors of every case above (largest first)."""
+    for tag, es, ea, ms, ma in sorted(ELEM_LOG, key=lambda r: -max(r[3] / max(r[1], 1e-300),
+                                                                    r[4] / max(r[2], 1e-300)))[:20]:
+        print(f"[elem] {tag}: l2 {es:.2e}/{ea:.2e} max {ms:.2e}/{ma:.2e} "
+              f"ratio {ms / max(es, 1e-300):.2f}/{ma / max(ea, 1e-300):.2f}", flush=True)

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
     assert "hvox_plan" in syms and "hvox_synthesis" in syms and "hvox_analysis" in syms and "hvox_free" in syms
     for s in syms:
         assert hasattr(lib, s), s
-    assert lib.hvox_version() == 100
+    assert lib.hvox_version() == 200
     assert lib.hvox_error_string(-3) == b"out of device memory"
 
 
@@ -245,3 +245,95 @@ def test_automatic_choice_is_never_worse_than_either_pure_mode():
     assert info["n_vis_chunks"] * info["n_sky_chunks"] > 100000
     assert info["n_pairs_nufft"] == 0
     assert info["direct_terms"] == float(req.uvw.shape[0]) * req.xyz.shape[0]
+
+
+def test_sub_problem_regions_stay_within_32_bit_indexing():
+    """The kernels index inside one grid region of a sub-problem in 32-bit
+    arithmetic.  A monolithic request whose single sub-problem would hold
+    ~1350^3 grid-1 cells (> 2^31 - 1, though every FFT length is ~2000 <= 4096)
+    is split into chunks whose regions fit; half the sky extent stays one
+    sub-problem."""
+    rng = np.random.default_rng(4)
+    uvw = rng.uniform(-1000.0, 1000.0, (60, 3))
+    xyz = rng.uniform(-0.26, 0.26, (50, 3))
+    with hv.Plan(uvw, xyz, 1e-4, "f32", host_only=True, direct_threshold=0.0, max_fft_bytes=math.inf) as p:
+        info = p.info()
+    assert info["n_vis_chunks"] * info["n_sky_chunks"] > 1
+    assert info["n_pairs_direct"] == 0
+    # grid 1 and the two FFT buffers are each about a third of the sub-problem's workspace
+    assert info["max_pair_workspace_bytes"] < 3 * 8 * (2 ** 31 - 1)
+    with hv.Plan(uvw, 0.5 * xyz, 1e-4, "f32", host_only=True, direct_threshold=0.0,
+                 max_fft_bytes=math.inf) as p:
+        info = p.info()
+    assert info["n_vis_chunks"] == 1 and info["n_sky_chunks"] == 1 and info["n_pairs_nufft"] == 1
+
+
+def test_forced_out_of_memory_knob(monkeypatch):
+    """HVOX_FORCE_OOM_BYTES: a plan whose device memory could exceed the limit
+    fails with HVOX_ERR_OOM (checked on the host, so host-only plans fail too);
+    without the knob, or with a limit above the plan's bound, it succeeds."""
+    wl = W.ska_like(n_pix=20000, n_ant=40, n_times=10)
+    with hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True, max_fft_bytes=8e6) as p:
+        need = p.info()["device_bytes"]
+    assert need > 16 * (wl.n_vis + wl.n_pix)
+    monkeypatch.setenv("HVOX_FORCE_OOM_BYTES", str(need - 1))
+    with pytest.raises(hv.HvoxError) as ei:
+        hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True, max_fft_bytes=8e6)
+    assert ei.value.code == -3 and "HVOX_FORCE_OOM_BYTES" in str(ei.value)
+    monkeypatch.setenv("HVOX_FORCE_OOM_BYTES", str(need))
+    with hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True, max_fft_bytes=8e6) as p:
+        assert p.info()["device_bytes"] == need
+
+
+def test_device_bytes_bound_covers_the_tables_and_workspace():
+    wl = W.ska_like(n_pix=20000, n_ant=40, n_times=10)
+    with hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True, max_fft_bytes=8e6, direct_threshold=0.0) as p:
+        inf = p.info()
+    assert inf["on_device"] == 0
+    assert inf["device_bytes"] >= inf["resident_bytes"] + inf["workspace_bytes"]
+    # coordinates, permutations, deconvolution and the accumulator alone
+    assert inf["resident_bytes"] >= (24 + 4 + 8) * (wl.n_vis + wl.n_pix) + 64 * max(wl.n_vis, wl.n_pix)
+
+
+def test_upload_without_gpu_fails_cleanly_and_keeps_the_host_plan():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    wl = W.compact_disk(n_vis=50, n_pix=60)
+    p = hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True)
+    with pytest.raises(RuntimeError):
+        p.upload()
+    assert p.info()["on_device"] == 0 and p.info()["n_vis_chunks"] >= 1
+    p.free()
+
+
+def test_allocator_hooks_must_come_in_pairs():
+    wl = W.compact_disk(n_vis=20, n_pix=20)
+    lib = hv.load_library()
+    o = H.HvoxOpts()
+    o.flags = H.HVOX_PLAN_HOST_ONLY
+    o.dev_alloc = H.TORCH_ALLOC
+    plan = ctypes.c_void_p()
+    uvw = np.ascontiguousarray(wl.uvw)
+    xyz = np.ascontiguousarray(wl.xyz)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = lib.hvox_plan(uvw.ctypes.data_as(dp), wl.n_vis, xyz.ctypes.data_as(dp), wl.n_pix, 1e-4, H.HVOX_F32,
+                       ctypes.byref(o), None, ctypes.byref(plan))
+    assert rc == -1 and plan.value is None
+    assert b"together" in lib.hvox_last_error()
+
+
+def test_deterministic_plan_orders_its_work():
+    """A deterministic plan never puts two sub-problems of one target chunk into
+    one batch (so interpolation adds without atomics) and launches its direct
+    blocks in layers; the split between NUFFT and direct work is unchanged."""
+    wl = W.ska_like(n_pix=20000, n_ant=40, n_times=10)
+    kw = dict(host_only=True, max_fft_bytes=4e6)
+    with hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", **kw) as p, \
+            hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", deterministic=True, **kw) as q:
+        a, b = p.info(), q.info()
+    assert b["flags"] & H.HVOX_DETERMINISTIC
+    assert (a["n_pairs_nufft"], a["n_pairs_direct"]) == (b["n_pairs_nufft"], b["n_pairs_direct"])
+    assert b["n_batches"] >= a["n_batches"]
+    if a["n_pairs_direct"]:
+        assert a["n_direct_layers"] == 1 and b["n_direct_layers"] >= 1
