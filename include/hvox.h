@@ -153,6 +153,7 @@ typedef struct {
     int32_t flags;            /* the plan's option flags */
     int32_t on_device;        /* 1 once the device part exists */
     int64_t n_direct_layers;  /* HVOX_DETERMINISTIC: launches of the direct sum per data-row group */
+    int64_t noalloc_scratch_bytes;  /* static scratch hvox_transform_noalloc needs for this plan */
 } hvox_plan_info_t;
 
 /* Per-kernel statistics of the calls since the last reset (HVOX_TIMING plans). */
@@ -215,6 +216,26 @@ int hvox_synthesis(hvox_plan_t plan, const void *sky, void *vis, int32_t ntrans,
 /* vis -> sky:  sky[t][n] = sum_k vis[t][k] exp(+2 pi i <p_k, r_n>)   (Eq. 3, the adjoint)
  * With HVOX_REAL_SKY the imaginary part of sky is set to 0. */
 int hvox_analysis(hvox_plan_t plan, const void *vis, void *sky, int32_t ntrans, void *stream);
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Runs synthesis (direction 0, as hvox_synthesis) or analysis (direction 1,
+ * as hvox_analysis) of `plan` with the same kernels, but the grid workspace,
+ * the staged sources and the float64 accumulator come from one static device
+ * buffer of HVOX_STATIC_SCRATCH_BYTES per GPU (held from the first call on
+ * that GPU until the process ends) instead of the plan's own.  The call
+ * allocates nothing: no hipMalloc / hipFree, no events (HVOX_TIMING is
+ * ignored).  Inputs and outputs are the caller's, as for hvox_synthesis.
+ * Scratch need of a plan: 16 * 4 * max(n_vis, n_pix) accumulator bytes +
+ * staged sources of its largest batch + its workspace_bytes, each rounded up
+ * to 256 bytes; a plan needing more than the buffer fails with HVOX_ERR_OOM
+ * (plan_info's workspace_bytes is bounded by the workspace_bytes option).
+ * Every call on one GPU shares that GPU's buffer and it keeps the last call's
+ * contents (each call clears what must start at zero): calls that overlap on
+ * one GPU race, so serialise them (e.g. one stream). */
+#define HVOX_STATIC_SCRATCH_BYTES (64u << 20)
+int hvox_transform_noalloc(hvox_plan_t plan, int32_t direction, const void *in, void *out, int32_t ntrans,
+                           void *stream);
 
 /* Release every resource of the plan (device memory after synchronising the
  * plan's last stream).  NULL is a no-op. */

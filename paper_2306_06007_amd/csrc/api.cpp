@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -634,6 +635,79 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
     return rc;
 }
 
+// ---- the static scratch of hvox_transform_noalloc ---------------------------------
+// One buffer per GPU in the library's device code; host code reaches it only
+// through the per-device address that hipGetSymbolAddress returns (the array's
+// name is a host-side stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[HVOX_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// address of this GPU's copy of `scratch`, looked up once per device (the
+// current device must be the plan's)
+hipError_t static_scratch(int device, void **ptr)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// bytes of the accumulator rows, staged sources and grid workspace a plan
+// takes from the static scratch, each rounded up to 256 bytes
+void static_scratch_layout(const HostPlan &hp, size_t *acc_b, size_t *stage_b, size_t *ws_b)
+{
+    const bool f64 = hp.prm.dtype == HVOX_F64;
+    int64_t max_pts = 0;
+    for (const DirPlan *dp : {&hp.syn, &hp.ana})
+        for (const Batch &b : dp->batches) max_pts = std::max(max_pts, b.pts);
+    *acc_b = align256(16 * static_cast<size_t>(kRowBatch) * static_cast<size_t>(std::max(hp.n_vis, hp.n_pix)));
+    *stage_b = align256((f64 ? sizeof(StagedSrc<double>) : sizeof(StagedSrc<float>)) * static_cast<size_t>(max_pts));
+    *ws_b = align256((f64 ? 16 : 8) * static_cast<size_t>(hp.ws_elems));
+}
+
+int transform_static(hvox_plan_s *pl, int32_t direction, const void *in, void *out, int32_t ntrans, void *stream)
+{
+    if (!pl) return fail(HVOX_ERR_STATE, "NULL plan");
+    if (pl->host_only) return fail(HVOX_ERR_STATE, "host-only plan cannot run transforms (hvox_plan_upload first)");
+    if (direction != 0 && direction != 1) return fail(HVOX_ERR_ARG, "direction must be 0 (synthesis) or 1 (analysis)");
+    if (ntrans < 1) return fail(HVOX_ERR_ARG, "ntrans must be >= 1");
+    const bool synthesis = direction == 0;
+    const HostPlan &hp = pl->hp;
+    const int64_t n_in = synthesis ? hp.n_pix : hp.n_vis;
+    const int64_t n_out = synthesis ? hp.n_vis : hp.n_pix;
+    if ((n_in > 0 && !in) || (n_out > 0 && !out)) return fail(HVOX_ERR_ARG, "NULL data pointer");
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(HVOX_ERR_HIP, "hipGetDevice failed");
+    if (cur != pl->device) return fail(HVOX_ERR_STATE, "the plan's device is not the current device");
+    // scratch layout: accumulator rows, staged sources, grid workspace
+    const bool f64 = hp.prm.dtype == HVOX_F64;
+    size_t acc_b, stage_b, ws_b;
+    static_scratch_layout(hp, &acc_b, &stage_b, &ws_b);
+    if (acc_b + stage_b + ws_b > HVOX_STATIC_SCRATCH_BYTES)
+        return fail(HVOX_ERR_OOM, "the plan needs " + std::to_string(acc_b + stage_b + ws_b) +
+                                      " bytes of scratch; the static buffer holds " +
+                                      std::to_string(static_cast<size_t>(HVOX_STATIC_SCRATCH_BYTES)));
+    void *base = nullptr;
+    const hipError_t e = static_scratch(cur, &base);
+    if (e != hipSuccess) return fail(HVOX_ERR_HIP, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+    char *b = static_cast<char *>(base);
+    const Scratch sc{b + acc_b + stage_b, b + acc_b, reinterpret_cast<double *>(b)};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (f64) return run_direction<double>(pl, synthesis, in, out, ntrans, st, sc, false);
+    return run_direction<float>(pl, synthesis, in, out, ntrans, st, sc, false);
+}
+
 // HVOX_FORCE_OOM_BYTES: fault injection (a plan may not hold more device memory)
 double forced_oom_limit()
 {
@@ -836,6 +910,16 @@ int hvox_plan_upload(hvox_plan_t plan, void *stream)
     return HVOX_OK;
 }
 
+int hvox_transform_noalloc(hvox_plan_t plan, int32_t direction, const void *in, void *out, int32_t ntrans,
+                           void *stream)
+{
+    try {
+        return transform_static(plan, direction, in, out, ntrans, stream);
+    } catch (...) {
+        return fail(HVOX_ERR_HIP, "unexpected failure in hvox_transform_noalloc");
+    }
+}
+
 int hvox_free(hvox_plan_t plan)
 {
     if (!plan) return HVOX_OK;
@@ -884,6 +968,9 @@ int hvox_plan_info(hvox_plan_t plan, hvox_plan_info_t *out)
     out->flags = hp.prm.flags;
     out->on_device = plan->host_only ? 0 : 1;
     out->n_direct_layers = static_cast<int64_t>(std::max<size_t>(hp.syn.direct_layer_off.size(), 1) - 1);
+    size_t acc_b, stage_b, ws_b;
+    static_scratch_layout(hp, &acc_b, &stage_b, &ws_b);
+    out->noalloc_scratch_bytes = static_cast<int64_t>(acc_b + stage_b + ws_b);
     return HVOX_OK;
 }
 

@@ -73,7 +73,7 @@ class HvoxPlanInfo(ctypes.Structure):
                 ("grid_cells", ctypes.c_double), ("direct_terms", ctypes.c_double),
                 ("est_seconds", ctypes.c_double), ("plan_seconds", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("flags", ctypes.c_int32), ("on_device", ctypes.c_int32),
-                ("n_direct_layers", ctypes.c_int64)]
+                ("n_direct_layers", ctypes.c_int64), ("noalloc_scratch_bytes", ctypes.c_int64)]
 
 
 class HvoxStats(ctypes.Structure):
@@ -81,7 +81,7 @@ class HvoxStats(ctypes.Structure):
                 ("alg_bytes", ctypes.c_double * len(KERNELS)), ("alg_flops", ctypes.c_double * len(KERNELS))]
 
 
-EXPORTS = ("hvox_plan", "hvox_plan_upload", "hvox_synthesis", "hvox_analysis", "hvox_free", "hvox_plan_info",
+EXPORTS = ("hvox_plan", "hvox_plan_upload", "hvox_synthesis", "hvox_transform_noalloc", "hvox_analysis", "hvox_free", "hvox_plan_info",
            "hvox_plan_permutation", "hvox_plan_chunks", "hvox_stats", "hvox_stats_reset", "hvox_set_timing",
            "hvox_kernel_params", "hvox_alg1", "hvox_partition", "hvox_error_string",
            "hvox_last_error", "hvox_version")
@@ -108,6 +108,8 @@ def load_library():
         f = getattr(lib, name)
         f.restype = ctypes.c_int
         f.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
+    lib.hvox_transform_noalloc.restype = ctypes.c_int
+    lib.hvox_transform_noalloc.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, vp]
     lib.hvox_plan_upload.restype = ctypes.c_int
     lib.hvox_plan_upload.argtypes = [vp, vp]
     lib.hvox_free.restype = ctypes.c_int
