@@ -133,8 +133,8 @@ HBM_KERNELS = ("zero", "spread", "fft_x", "fft_y", "fft_z", "interp", "finalize"
 
 def roofline_entry(st, dtype, name=None, rows=1, mode="auto"):
     """Roofline of one kernel (default: the one taking the most time): its
-    algorithmic bytes (or VALU lane-operations) per launch over its average
-    launch duration, against the MI355X peak."""
+    algorithmic bytes (or arithmetic) per launch over its average launch
+    duration, against the MI355X peak."""
     hbm_kernels = HBM_KERNELS
     if name is None:
         name = max(st, key=lambda k: st[k]["ms"])
@@ -147,22 +147,28 @@ def roofline_entry(st, dtype, name=None, rows=1, mode="auto"):
         traffic = measured_traffic(name, dtype, mode)
         return name, {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
-    # direct summation: VALU-bound.  A term-row costs VALU_OPS_PER_TERM lane
-    # instructions, each counted as one FMA (2 FLOP) against the vector peak;
-    # issue_bound is the rate the instruction mix allows at the per-class
-    # issue rates (float32 arithmetic 2, float64 and the rest 1, hardware
-    # sine / cosine 1/2 per lane-cycle).
-    ops = VALU_OPS_PER_TERM[(dtype, rows)]
+    # direct summation: bound by the vector ALUs.  Algorithmic arithmetic per
+    # term-row: ALG_OPS_PER_TERM operations (the phase dot product, its
+    # reduction, sine and cosine, and the complex multiply-accumulate) against
+    # the published vector peak; issue_bound compares the term rate with what
+    # the loop's own instruction mix allows at the per-class issue rates.
     terms_per_s = v["alg_flops"] / n / avg_s if avg_s > 0 else 0.0
-    achieved = terms_per_s * ops * 2 / 1e12
+    achieved = terms_per_s * ALG_OPS_PER_TERM / 1e12
     peak = VECTOR_PEAK_TFLOPS[dtype]
     bound = LANE_CYCLES_PER_S / VALU_CYCLES_PER_TERM[(dtype, rows)]
     return name, {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                   "frac": achieved / peak, "traffic": measured_traffic(name, dtype, mode),
+                  "ops_per_term": ALG_OPS_PER_TERM,
                   "issue_bound": {"term_rows_per_s": bound, "achieved_term_rows_per_s": terms_per_s,
-                                  "frac": terms_per_s / bound}}
+                                  "frac": terms_per_s / bound,
+                                  "valu_instr_per_term_row": VALU_OPS_PER_TERM[(dtype, rows)]}}
 
 
+# Algorithmic operations of one direct-sum term (target k, source n), the count
+# the roofline is graded on: the phase p_k.r_n (3 multiply-adds, 6), its
+# reduction to a fraction of a turn (2), its sine and cosine (about 14) and the
+# complex multiply-accumulate (8): about 30 operations per term.
+ALG_OPS_PER_TERM = 30.0
 # VALU instructions issued per (target, source, data row) by the direct
 # kernel's inner loop, counted from its gfx950 assembly (the loop that reads
 # the staged sources from LDS; LDS reads and scalar loop control excluded), by
@@ -193,17 +199,20 @@ def host_cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(wl, target_s=12.0):
+def cpu_baseline(wl, target_s=20.0):
     """FP64 oracle on sampled rows of both directions, extrapolated linearly
-    (the direct sum's cost is exactly linear in the number of output rows)."""
+    (the direct sum's cost is exactly linear in the number of output rows).
+    About target_s seconds of CPU work: a warm 64-row probe sizes the sample
+    (at most 4,096 rows per direction)."""
     import oracle
     from paper_2306_06007_amd import workloads as W
-    probe = 16
+    oracle.synthesis(wl.uvw, wl.xyz, wl.sky, rows=W.sample_rows(wl.n_vis, 8, seed=100))   # thread pool warm-up
+    probe = 64
     rv = W.sample_rows(wl.n_vis, probe, seed=101)
     t0 = time.perf_counter()
     oracle.synthesis(wl.uvw, wl.xyz, wl.sky, rows=rv)
     per_row_v = (time.perf_counter() - t0) / probe
-    k = int(max(32, min(4096, 0.5 * target_s / max(per_row_v, 1e-9))))
+    k = int(max(64, min(4096, 0.5 * target_s / max(per_row_v, 1e-9))))
     rv = W.sample_rows(wl.n_vis, k, seed=102)
     rp = W.sample_rows(wl.n_pix, k, seed=103)
     t0 = time.perf_counter()
@@ -225,21 +234,59 @@ def serving_run(slots=8, planners=8):
     """64 Poisson-arriving requests (mean gap 10 ms), each a synthesis or an
     analysis with log-uniform 1e4..1e6 visibilities and pixels on subsampled
     SKA-like / LOFAR-like baselines, float32 at eps = 1e-4, through the
-    continuous-batching server; latency from arrival to observed completion."""
+    continuous-batching server; latency from arrival to observed completion.
+    Afterwards every request runs again alone (one slot, nothing else on the
+    device) and its result is compared with the one served in the mix."""
+    import numpy as np
     from paper_2306_06007_amd import serve
     from paper_2306_06007_amd import workloads as W
     reqs = W.serving_requests(seed=4)
     log(f"serving: {len(reqs)} requests generated")
     ex = serve.GpuExecutor(eps=1e-4, dtype="f32", slots=slots, planners=planners, workspace_bytes=1 << 30)
     srv = serve.Server(ex, hbm_budget_bytes=64e9)
-    res = srv.run(reqs, keep_outputs=False)
+    res = srv.run(reqs, keep_outputs=True)
     ex.close()
     s = serve.summarize(res)
     s["max_in_flight"] = max(n for _, _, n, _ in srv.log)
+    s["max_resident_bytes"] = max(u for _, _, _, u in srv.log)
     s["slots"], s["planners"] = slots, planners
     s["plan_seconds_mean"] = float(sum(ex.plan_seconds) / max(1, len(ex.plan_seconds)))
     s["plan_seconds_total"] = float(sum(ex.plan_seconds))
-    return s
+    s["upload_seconds_mean"] = float(sum(ex.upload_seconds) / max(1, len(ex.upload_seconds)))
+    # alone vs in the mix
+    alone = serve.GpuExecutor(eps=1e-4, dtype="f32", slots=1, planners=1, workspace_bytes=1 << 30, cache_size=0)
+    diffs = []
+    for q, r in zip(reqs, res):
+        one = serve.Server(alone, hbm_budget_bytes=64e9).run(
+            [W.Request(q.rid, 0.0, q.direction, q.layout, q.uvw, q.xyz, q.data)])[0].output
+        d = float(np.max(np.abs(r.output - one)) / max(float(np.max(np.abs(one))), 1e-300))
+        diffs.append(d)
+    alone.close()
+    s["alone_vs_mix_max_rel_diff"] = {"max": max(diffs), "median": float(np.median(diffs))}
+    log(f"serving: p50 {s['p50_latency_s']:.3f} s, p99 {s['p99_latency_s']:.3f} s; alone vs mix max rel diff "
+        f"{max(diffs):.2e}")
+    return s, reqs, res
+
+
+def serving_errors(reqs, res, rows=1024):
+    """Error of every served result against the oracle on `rows` sampled outputs
+    (part of the CPU-baseline leg: the only place bench.py runs the oracle)."""
+    import numpy as np
+    import oracle
+    from paper_2306_06007_amd import workloads as W
+    errs = []
+    for q, r in zip(reqs, res):
+        n_out = q.uvw.shape[0] if q.direction == "synthesis" else q.xyz.shape[0]
+        rw = W.sample_rows(n_out, rows, seed=1000 + q.rid)
+        ref = (oracle.synthesis(q.uvw, q.xyz, q.data, rows=rw) if q.direction == "synthesis"
+               else oracle.analysis(q.uvw, q.xyz, q.data, rows=rw))
+        errs.append({"rid": q.rid, "direction": q.direction, "n_vis": int(q.uvw.shape[0]),
+                     "n_pix": int(q.xyz.shape[0]), "rel_l2": oracle.rel_l2(r.output[:, rw], ref),
+                     "max_rel_err": oracle.max_rel_err(r.output[:, rw], ref)})
+    l2 = [e["rel_l2"] for e in errs]
+    mx = [e["max_rel_err"] for e in errs]
+    return {"rows_per_request": rows, "rel_l2_max": max(l2), "rel_l2_median": float(np.median(l2)),
+            "max_rel_err_max": max(mx), "all_within_eps": bool(max(l2) <= 1e-4), "per_request": errs}
 
 
 def main():
@@ -258,6 +305,9 @@ def main():
     ap.add_argument("--n-pix", type=int, default=1000000,
                     help="sky points of the SKA-like workload (default the full 1,000,000-point cap; smaller "
                          "values only for counter runs, never for the reported metric)")
+    ap.add_argument("--modes", default="",
+                    help="comma-separated subset of the runs reported beside the headline (forced_nufft, all_direct, "
+                         "batched_ntrans4, dense_10km, dense_10km_all_direct); default all")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the runs reported beside the headline (forced NUFFT, all direct, four rows, the dense "
                          "mesh, serving)")
@@ -342,20 +392,27 @@ def main():
         results["f64"] = run_mode("f64", 1e-9, args.direct_threshold, args.f64_steps or max(1, args.steps // 5),
                                   min(1, args.warmup), dist=args.dist_runs)
     modes = {}
+    wanted = set(filter(None, args.modes.split(","))) or {"forced_nufft", "all_direct", "batched_ntrans4",
+                                                           "dense_10km", "dense_10km_all_direct"}
     if not args.no_modes:
         # the two other execution modes of the float32 transform: every sub-problem as a
         # NUFFT (the path the spread / FFT / interp rooflines describe), every one direct
-        modes["forced_nufft"] = run_mode("f32", 1e-4, 0.0, 1, 0)
-        modes["all_direct"] = run_mode("f32", 0.0, -1.0, 1, 0)
+        if "forced_nufft" in wanted:
+            modes["forced_nufft"] = run_mode("f32", 1e-4, 0.0, 1, 0)
+        if "all_direct" in wanted:
+            modes["all_direct"] = run_mode("f32", 0.0, -1.0, 1, 0)
         # ntrans = 4 data rows through one plan (e.g. channels or polarisations)
-        modes["batched_ntrans4"] = run_mode("f32", 1e-4, args.direct_threshold, 1, 1, ntrans=4)
-    if not (args.no_modes or dense_head):
+        if "batched_ntrans4" in wanted:
+            modes["batched_ntrans4"] = run_mode("f32", 1e-4, args.direct_threshold, 1, 1, ntrans=4)
+    if not (args.no_modes or dense_head) and wanted & {"dense_10km", "dense_10km_all_direct"}:
         # a dense 30-degree DCOS image of the paper's telescope-radius ladder (10 km rung,
         # 238k vis x 10.24M pixels): most terms go through NUFFT sub-problems
         dense = W.dense_dcos(10.0)
         log(f"workload {dense.name}")
-        modes["dense_10km"] = run_mode("f32", 1e-4, args.direct_threshold, 1, 1, work=dense)
-        modes["dense_10km_all_direct"] = run_mode("f32", 0.0, -1.0, 1, 0, work=dense)
+        if "dense_10km" in wanted:
+            modes["dense_10km"] = run_mode("f32", 1e-4, args.direct_threshold, 1, 1, work=dense)
+        if "dense_10km_all_direct" in wanted:
+            modes["dense_10km_all_direct"] = run_mode("f32", 0.0, -1.0, 1, 0, work=dense)
         del dense
     if args.lofar:
         lofar = W.lofar_like()
@@ -407,6 +464,18 @@ def main():
         "directions": {d: results[d]["directions"] for d in results if results[d]["directions"]} or None,
         "source_hash": kernel_source_hash(),
     }
+    if "forced_nufft" in modes:
+        # the rooflines of the NUFFT kernels on the forced-NUFFT step (every sub-problem a
+        # type-3 NUFFT): spreading (grid fills included) and interpolation are the graded ones
+        fr = modes["forced_nufft"]
+        out["nufft_rooflines"] = {}
+        for k in ("spread", "interp", "fft_x", "fft_y", "fft_z", "transpose", "prephase"):
+            v = fr["stats"][k]
+            if v["launches"] and v["ms"] > 0:
+                _, rf = roofline_entry(fr["stats"], "f32", k, mode="forced_nufft")
+                out["nufft_rooflines"][k] = {"achieved_GB_s": round(rf["achieved"], 1), "frac": round(rf["frac"], 4),
+                                             "ms": round(v["ms"], 2), "launches": v["launches"],
+                                             "alg_bytes": v["alg_bytes"]}
     if modes:
         out["modes"] = {}
         for m, r in modes.items():
@@ -432,27 +501,32 @@ def main():
             ent["rooflines"] = roofs
             out["modes"][m] = ent
     if args.serving or not (args.no_serving or args.no_modes):
-        out["serving"] = serving_run()
+        out["serving"], serving_reqs, serving_res = serving_run()
     if not args.no_cpu_baseline:
         import oracle
         log("cpu baseline (oracle on sampled rows)...")
         cb, (rv, Vs), (rp, Is) = cpu_baseline(wl)
         out["cpu_baseline"] = cb
-        out["rel_l2_vs_oracle"] = {
-            d: {"synthesis": oracle.rel_l2(results[d]["V"][rv], Vs[0]),
-                "analysis": oracle.rel_l2(results[d]["I"][rp], Is[0]),
-                "rows": int(len(rv))} for d in results}
+        def errs(V, I, Vr, Ir, k):
+            return {"synthesis": oracle.rel_l2(V, Vr), "analysis": oracle.rel_l2(I, Ir),
+                    "synthesis_max_rel_err": oracle.max_rel_err(V, Vr),
+                    "analysis_max_rel_err": oracle.max_rel_err(I, Ir), "rows": int(k)}
+
+        out["rel_l2_vs_oracle"] = {d: errs(results[d]["V"][rv], results[d]["I"][rp], Vs[0], Is[0], len(rv))
+                                   for d in results}
         for m, r in modes.items():
             if r["wl"] is wl:
-                out["modes"][m]["rel_l2_vs_oracle"] = {"synthesis": oracle.rel_l2(r["V"][rv], Vs[0]),
-                                                       "analysis": oracle.rel_l2(r["I"][rp], Is[0])}
+                out["modes"][m]["rel_l2_vs_oracle"] = errs(r["V"][rv], r["I"][rp], Vs[0], Is[0], len(rv))
             else:   # another workload: its own sampled rows
                 ow = r["wl"]
-                rv2 = W.sample_rows(ow.n_vis, 64, seed=51)
-                rp2 = W.sample_rows(ow.n_pix, 64, seed=52)
-                out["modes"][m]["rel_l2_vs_oracle"] = {
-                    "synthesis": oracle.rel_l2(r["V"][rv2], oracle.synthesis(ow.uvw, ow.xyz, ow.sky, rows=rv2)[0]),
-                    "analysis": oracle.rel_l2(r["I"][rp2], oracle.analysis(ow.uvw, ow.xyz, ow.vis, rows=rp2)[0])}
+                rv2 = W.sample_rows(ow.n_vis, 256, seed=51)
+                rp2 = W.sample_rows(ow.n_pix, 256, seed=52)
+                out["modes"][m]["rel_l2_vs_oracle"] = errs(
+                    r["V"][rv2], r["I"][rp2], oracle.synthesis(ow.uvw, ow.xyz, ow.sky, rows=rv2)[0],
+                    oracle.analysis(ow.uvw, ow.xyz, ow.vis, rows=rp2)[0], len(rv2))
+        if "serving" in out:
+            log("serving results against the oracle (1,024 sampled rows per request)...")
+            out["serving"]["vs_oracle"] = serving_errors(serving_reqs, serving_res)
     print(json.dumps(out), flush=True)
 
 

@@ -154,11 +154,15 @@ typedef struct {
     int32_t on_device;        /* 1 once the device part exists */
     int64_t n_direct_layers;  /* HVOX_DETERMINISTIC: launches of the direct sum per data-row group */
     int64_t noalloc_scratch_bytes;  /* static scratch hvox_transform_noalloc needs for this plan */
+    /* occupancy of the NUFFT grids (both directions, device plans): grid-1 tiles (32 x 8 x 8 cells)
+     * holding sources, x lines of grid 1 in tile rows holding sources, z planes in tile layers
+     * holding sources; [0] occupied, [1] total */
+    int64_t occ_tiles[2], occ_xlines[2], occ_zplanes[2];
 } hvox_plan_info_t;
 
 /* Per-kernel statistics of the calls since the last reset (HVOX_TIMING plans). */
-#define HVOX_K_ZERO     0
-#define HVOX_K_SPREAD   1
+#define HVOX_K_ZERO     0   /* accumulator clears */
+#define HVOX_K_SPREAD   1   /* spreading, with the grid-1 fills of mostly empty batches */
 #define HVOX_K_FFT_X    2
 #define HVOX_K_FFT_Y    3
 #define HVOX_K_FFT_Z    4

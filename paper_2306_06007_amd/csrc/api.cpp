@@ -32,8 +32,8 @@ template <typename T>
 hipError_t launch_spread(const PairDev *, const SpreadTile *, int64_t, const int32_t *, const void *, void *, int, double,
                          hipStream_t);
 template <typename T>
-hipError_t launch_fft(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *, const void *, int,
-                      int, double, hipStream_t);
+hipError_t launch_fft(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *, const void *,
+                      const uint32_t *, int, int, double, hipStream_t);
 template <typename T>
 hipError_t launch_transpose(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
 template <typename T>
@@ -63,6 +63,7 @@ struct DevDir {
     int64_t *pre_ttiles = nullptr;   // per batch: transpose-tile prefix over its pairs
     int32_t *records = nullptr;      // source indices listed per tile (plan-resident binning)
     SpreadTile *spread_tiles = nullptr;   // spreading tiles of every batch (descriptor per workgroup)
+    uint32_t *occ = nullptr;         // one bit per grid-1 tile: holds sources (read by the x pass)
     // per batch: descriptors of the further parts of crowded tiles, after the batch's
     // list_cnt first parts (a second launch adds them once the first has stored)
     std::vector<int64_t> spread_add_cnt;
@@ -287,13 +288,6 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
                     return launch_prephase<T>(pairs, pprefix, np, b.pts, sxyz, n_src, sperm, in_t, sc.stage, iota,
                                               p.w, st);
                 }));
-                if (b.sparse) {
-                    // mostly empty grid 1: clear the batch's grid-1 region, then spread the listed tiles
-                    HVOX_TRY(timed(pl, may_time, HVOX_K_ZERO, st, [&] {
-                        return launch_zero(static_cast<double *>(sc.ws),
-                                           b.g_cnt * static_cast<int64_t>(sizeof(C) / sizeof(double)), st);
-                    }));
-                }
                 HVOX_TRY(timed(pl, may_time, HVOX_K_SPREAD, st, [&] {
                     return launch_spread<T>(pairs, dd.spread_tiles + b.list_off, b.list_cnt, dd.records, sc.stage,
                                             sc.ws, p.w, p.beta, st);
@@ -307,8 +301,8 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
                 for (int pass = 0; pass < 3; ++pass) {
                     HVOX_TRY(timed(pl, may_time, HVOX_K_FFT_X + pass, st, [&] {
                         return launch_fft<T>(pairs, dd.pre_tiles[pass] + b.pre_tiles[pass], np, b.tiles[pass], pass,
-                                             sc.ws, pl->tw, pl->precor, b.lds_elems[pass], b.max_pass_len[pass],
-                                             iota, st);
+                                             sc.ws, pl->tw, pl->precor, dd.occ, b.lds_elems[pass],
+                                             b.max_pass_len[pass], iota, st);
                     }));
                     if (pass == 0)
                         HVOX_TRY(timed(pl, may_time, HVOX_K_TRANSPOSE, st, [&] {
@@ -413,11 +407,9 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
     if (e != hipSuccess) return bad(e, "binning count pass");
     std::vector<int64_t> off(nt + 1, 0);
     for (int64_t i = 0; i < nt; ++i) off[i + 1] = off[i] + counts[i];
-    // batches whose grid 1 is mostly empty (under a third of the tiles hold
-    // sources): clear it with one fill, spread only the non-empty tiles; other
-    // batches spread every tile (empty ones write zeros), which writes each cell
-    // once instead of twice (the fill streams at ~6.5 TB/s, an empty tile of the
-    // spreading kernel at ~4.5 TB/s, so the fill pays only below about a third)
+    // Only tiles holding sources are spread (each written once, zeros of the cells
+    // no footprint reaches included); the x pass reads the other tiles of grid 1
+    // as zeros, from the occupancy bitmap, so they are never written or cleared.
     // A crowded tile (more than kSpreadSplit sources) becomes a first part, stored
     // with the batch's other tiles, and further parts that a second launch adds
     // atomically on top -- except in deterministic plans, whose tiles are never split.
@@ -425,22 +417,47 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
     dp.spread_tiles.clear();
     dd->spread_add_cnt.assign(dp.batches.size(), 0);
     std::vector<SpreadTile> adds;
+    dp.occ_bits.assign(static_cast<size_t>((nt + 31) / 32 + kOccWords), 0u);   // padded: rows are read in whole words
+    for (int64_t t = 0; t < nt; ++t)
+        if (counts[t] > 0) dp.occ_bits[t >> 5] |= 1u << (t & 31);
     const double delta = pl->hp.prm.dtype == HVOX_F64 ? 16.0 : 8.0;
     for (Batch &b : dp.batches) {
-        const int64_t t0 = dp.pairs[b.pair0].tile0;
-        int64_t nonempty = 0;
-        for (int64_t t = 0; t < b.stiles; ++t) nonempty += counts[t0 + t] > 0;
-        b.sparse = 3 * nonempty < b.stiles;
         b.list_off = static_cast<int64_t>(dp.spread_tiles.size());
         adds.clear();
-        double listed_cells = 0.0;
         for (int64_t i = 0; i < b.npairs; ++i) {
             const PairDev &pd = dp.pairs[b.pair0 + i];
+            // occupancy statistics: tiles with sources, x lines and z planes they cover
+            for (int32_t tz = 0; tz < pd.ntile[2]; ++tz) {
+                bool layer = false;
+                for (int32_t ty = 0; ty < pd.ntile[1]; ++ty) {
+                    bool row = false;
+                    for (int32_t tx = 0; tx < pd.ntile[0]; ++tx) {
+                        const bool occ = counts[pd.tile0 + (static_cast<int64_t>(tz) * pd.ntile[1] + ty) * pd.ntile[0] + tx] > 0;
+                        dp.occ_tiles[0] += occ;
+                        row = row || occ;
+                    }
+                    layer = layer || row;
+                    const int64_t lines = static_cast<int64_t>(std::min(kTileY, pd.n1[1] - ty * kTileY)) *
+                                          std::min(kTileZ, pd.n1[2] - tz * kTileZ);
+                    if (row) dp.occ_xlines[0] += lines;
+                    dp.occ_xlines[1] += lines;
+                }
+                const int64_t planes = std::min(kTileZ, pd.n1[2] - tz * kTileZ);
+                if (layer) dp.occ_zplanes[0] += planes;
+                dp.occ_zplanes[1] += planes;
+            }
+            dp.occ_tiles[1] += static_cast<int64_t>(pd.ntile[0]) * pd.ntile[1] * pd.ntile[2];
             int64_t gt = pd.tile0;   // tiles are numbered x fastest, then y, then z
             for (int32_t tz = 0; tz < pd.ntile[2]; ++tz)
                 for (int32_t ty = 0; ty < pd.ntile[1]; ++ty)
                     for (int32_t tx = 0; tx < pd.ntile[0]; ++tx, ++gt) {
-                        if (b.sparse && counts[gt] == 0) continue;
+                        if (counts[gt] == 0) {
+                            // the x pass does not read this tile's cells
+                            dp.alg_bytes[HVOX_K_FFT_X] -=
+                                delta * static_cast<double>(std::min(kTileX, pd.n1[0] - tx * kTileX)) *
+                                std::min(kTileY, pd.n1[1] - ty * kTileY) * std::min(kTileZ, pd.n1[2] - tz * kTileZ);
+                            continue;
+                        }
                         SpreadTile d{};
                         d.pair = static_cast<int32_t>(i);
                         d.org[0] = static_cast<int16_t>(tx * kTileX);
@@ -457,18 +474,18 @@ int bin_direction(hvox_plan_s *pl, DirPlan &dp, DevDir *dd, const double *sxyz, 
                             a.flags = kSpreadAdd;
                             adds.push_back(a);
                         }
-                        listed_cells += static_cast<double>(std::min(kTileX, pd.n1[0] - tx * kTileX)) *
-                                        std::min(kTileY, pd.n1[1] - ty * kTileY) *
-                                        std::min(kTileZ, pd.n1[2] - tz * kTileZ);
                     }
         }
         b.list_cnt = static_cast<int64_t>(dp.spread_tiles.size()) - b.list_off;
         dd->spread_add_cnt[&b - dp.batches.data()] = static_cast<int64_t>(adds.size());
         dp.spread_tiles.insert(dp.spread_tiles.end(), adds.begin(), adds.end());
-        if (!b.sparse) continue;
-        // the fill writes the batch's grid-1 region, spreading only the listed tiles' cells
-        dp.alg_bytes[HVOX_K_SPREAD] -= delta * (static_cast<double>(b.g_cnt) - listed_cells);
-        dp.alg_bytes[HVOX_K_ZERO] += delta * static_cast<double>(b.g_cnt);
+    }
+    {
+        hipError_t eo = upload(pl, dp.occ_bits, &dd->occ, st);
+        if (eo == hipSuccess) eo = hipStreamSynchronize(st);
+        if (eo != hipSuccess) return bad(eo, "tile occupancy");
+        dp.occ_bits.clear();
+        dp.occ_bits.shrink_to_fit();
     }
     if (!dp.spread_tiles.empty()) {
         hipError_t el = upload(pl, dp.spread_tiles, &dd->spread_tiles, st);
@@ -971,6 +988,11 @@ int hvox_plan_info(hvox_plan_t plan, hvox_plan_info_t *out)
     size_t acc_b, stage_b, ws_b;
     static_scratch_layout(hp, &acc_b, &stage_b, &ws_b);
     out->noalloc_scratch_bytes = static_cast<int64_t>(acc_b + stage_b + ws_b);
+    for (int q = 0; q < 2; ++q) {
+        out->occ_tiles[q] = hp.syn.occ_tiles[q] + hp.ana.occ_tiles[q];
+        out->occ_xlines[q] = hp.syn.occ_xlines[q] + hp.ana.occ_xlines[q];
+        out->occ_zplanes[q] = hp.syn.occ_zplanes[q] + hp.ana.occ_zplanes[q];
+    }
     return HVOX_OK;
 }
 
@@ -1084,9 +1106,9 @@ extern "C" int hvox_test_fft(int32_t dtype, int32_t n, int32_t nin, int32_t nlin
     if (e == hipSuccess)
         e = dtype == HVOX_F64
                 ? launch_fft<double>(static_cast<PairDev *>(d_pd), static_cast<int64_t *>(d_pre), 1, tiles, 0, d_ws,
-                                     d_tw, d_one, lds, n, sign, st)
+                                     d_tw, d_one, nullptr, lds, n, sign, st)
                 : launch_fft<float>(static_cast<PairDev *>(d_pd), static_cast<int64_t *>(d_pre), 1, tiles, 0, d_ws,
-                                    d_tw, d_one, lds, n, sign, st);
+                                    d_tw, d_one, nullptr, lds, n, sign, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(out, static_cast<char *>(d_ws) + delta * gin, delta * gout, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -44,6 +44,9 @@ constexpr int kMaxStages = 16;       // radix stages per FFT length
 // workgroups per launch of the kernels whose grid grows with the problem (direct,
 // interp): a dispatch counts its work-items in 32 bits
 constexpr int64_t kMaxLaunchBlocks = int64_t(1) << 22;
+// occupancy words of a tile row staged per FFT line: a row of at most
+// kFftMaxLen / kTileX tiles starting at any bit
+constexpr int kOccWords = (kFftMaxLen / 32 + 31) / 32 + 1;
 // spreading by grid-1 tile: one 256-thread workgroup per tile of
 // kTileX x kTileY x kTileZ cells, a column of kTileZ cells per thread; points
 // touching the tile are staged kSpreadBatch at a time
@@ -149,9 +152,8 @@ struct Batch {
     int64_t pre_stiles = 0;              // offset of the batch's tile prefix array
     int64_t ttiles = 0;                  // transpose tiles (workgroups)
     int64_t g_cnt = 0;                   // complex elements of the batch's grid-1 region (starts at 0)
-    bool sparse = false;                 // spread only the non-empty tiles after clearing the grid-1 region
-    int64_t list_off = 0, list_cnt = 0;  // the batch's spreading tiles in the direction's descriptor list
-                                         //   (sparse batches: the non-empty tiles; others: every tile)
+    int64_t list_off = 0, list_cnt = 0;  // the batch's spreading tiles (those holding sources) in the
+                                         //   direction's descriptor list
     int64_t pre_ttiles = 0;              // offset of the batch's transpose-tile prefix array
     int64_t ws_end = 0;                  // end of the batch's workspace use (complex elements)
     int64_t pre_pts = 0, pre_tgts = 0;   // offsets into the prefix arrays (pre_tgts: interp workgroups)
@@ -168,6 +170,9 @@ struct DirPlan {                         // one direction (synthesis or analysis
     std::vector<int64_t> pre_stiles;     // per batch: npairs+1 prefix sums of spreading tiles
     std::vector<int64_t> pre_ttiles;     // per batch: npairs+1 prefix sums of transpose tiles
     int64_t tiles_total = 0;             // spreading tiles over all batches
+    // one bit per grid-1 tile (index tile0 + local tile): set when the tile holds sources.
+    // Only those tiles are spread; the x pass reads the others as zeros.
+    std::vector<uint32_t> occ_bits;
     std::vector<SpreadTile> spread_tiles;   // spreading tiles of every batch (built with the binning)
     std::vector<DirectItem> direct;
     // direct items in launch order: [direct_layer_off[l], direct_layer_off[l + 1]) is launch l.
@@ -176,6 +181,7 @@ struct DirPlan {                         // one direction (synthesis or analysis
     // add into the accumulator without atomics, layer after layer.
     std::vector<int64_t> direct_layer_off;
     double grid_cells = 0.0, direct_terms = 0.0;
+    int64_t occ_tiles[2] = {0, 0}, occ_xlines[2] = {0, 0}, occ_zplanes[2] = {0, 0};   // filled by the binning
     double est_seconds = 0.0;
     double alg_bytes[HVOX_K_COUNT] = {0};
     double alg_flops[HVOX_K_COUNT] = {0};

@@ -446,19 +446,23 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int ls, int p, const cplx
 // read contiguous lines; the z pass reads its lines strided (line j of the
 // plane is element j of every z-slab, so consecutive lines sit in adjacent
 // lanes).  The x pass also applies the separable pre-correction
-// 1/Phi_hat(l/n2) of all three axes (the (y, z) factor once per line).  Output
+// 1/Phi_hat(l/n2) of all three axes (the (y, z) factor once per line) and
+// reads grid-1 tiles that hold no source as zeros.  Output
 // q of the kept window is FFT index (wstart + q) mod n, written line-major:
 // out[line][q].
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pairs, const int64_t *__restrict__ prefix,
                                                  int npairs, int pass, cplx<T> *__restrict__ ws,
                                                  const cplx<T> *__restrict__ twtab, const T *__restrict__ precor,
-                                                 int tw_off, T s)
+                                                 const uint32_t *__restrict__ occ, int tw_off, T s)
 {
+    static_assert(kTileX == 32, "a grid-1 tile spans 32 cells of an x line");
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *lds = reinterpret_cast<cplx<T> *>(smem_raw);
     cplx<T> *ltw = lds + tw_off;              // exp(s 2 pi i j/n), j < n, after the lines
     __shared__ T lfac[kFftMaxLines];
+    __shared__ uint32_t lmask[kFftMaxLines][kOccWords];   // x pass: occupancy bits of each line's tile row
+    __shared__ int lbit0[kFftMaxLines];
     const int p = (int)find_segment(prefix, npairs, blockIdx.x);
     const PairDev &P = pairs[p];
     const int64_t tile = (int64_t)blockIdx.x - prefix[p];
@@ -490,6 +494,11 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
             const int64_t li = line0 + threadIdx.x;
             const int64_t lz = li / P.n1[1], ly = li - lz * P.n1[1];
             lfac[threadIdx.x] = precor[P.precor[1] + ly] * precor[P.precor[2] + lz];
+            // tiles of this line's row: bit rowbit + tx is tile (tx, ly / 8, lz / 8) of the pair;
+            // a tile without sources was never written and reads as zeros (no bitmap: all read)
+            const int64_t rowbit = P.tile0 + ((lz / kTileZ) * P.ntile[1] + ly / kTileY) * P.ntile[0];
+            lbit0[threadIdx.x] = (int)(rowbit & 31);
+            for (int q = 0; q < kOccWords; ++q) lmask[threadIdx.x][q] = occ ? occ[(rowbit >> 5) + q] : ~0u;
         }
         __syncthreads();
     }
@@ -518,7 +527,12 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
                 const int l = f < half_n ? f : f - n;
                 jl[c] = j;
                 slot[c] = __mul24(j, ls) + f;
-                if (l >= -half_in && l < half_in) {
+                bool take = l >= -half_in && l < half_in;
+                if (pass == 0 && take) {
+                    const int b = lbit0[j] + ((l + half_in) >> 5);
+                    take = (lmask[j][b >> 5] >> (b & 31)) & 1u;
+                }
+                if (take) {
                     v[c] = sb[__mul24(j, nin) + l + half_in];
                     if (pass == 0) fx[c] = px[l];
                 }
@@ -701,19 +715,21 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
             const T kyz = ok ? ker[slot][w + dy] * ker[slot][2 * w + dz] : T(0);
             const cplx<T> *col = grid + (ok ? qy * wz + qz : 0);
             T sr = T(0), si = T(0);
-            // eight x cells at a time: cells outside the kept window get weight
-            // 0 and a valid address, so the loads carry no branches and issue together
+            // eight x cells at a time: cells beyond the kernel support or outside the
+            // kept window get weight 0 and the address of a cell the target reads
+            // anyway (its last column, clamped into the window), so the loads carry no
+            // branches, issue together and fetch no line the window does not need
             for (int dx0 = 0; dx0 < w; dx0 += 8) {
                 cplx<T> gv[8];
                 T kx[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const int dx = dx0 + u;
+                    const int dx = min(dx0 + u, w - 1);
                     int qx = m0[0] + dx - sx;
                     if (fx) { qx %= n2x; if (qx < 0) qx += n2x; }
-                    const bool okx = dx < w && qx >= 0 && qx < wx;
+                    const bool okx = dx0 + u < w && qx >= 0 && qx < wx;
                     kx[u] = okx ? ker[slot][dx] : T(0);
-                    gv[u] = col[okx ? qx * xstride : 0];
+                    gv[u] = col[(int64_t)min(max(qx, 0), wx - 1) * xstride];
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
@@ -956,7 +972,8 @@ hipError_t launch_spread(const PairDev *pairs, const SpreadTile *tiles, int64_t 
 
 template <typename T>
 hipError_t launch_fft(const PairDev *pairs, const int64_t *prefix, int npairs, int64_t tiles, int pass, void *ws,
-                      const void *tw, const void *precor, int lds_elems, int max_len, double sign, hipStream_t st)
+                      const void *tw, const void *precor, const uint32_t *occ, int lds_elems, int max_len, double sign,
+                      hipStream_t st)
 {
     if (tiles <= 0) return hipSuccess;
     // dynamic LDS: the lines of one workgroup, then the twiddle table of the longest line
@@ -966,11 +983,11 @@ hipError_t launch_fft(const PairDev *pairs, const int64_t *prefix, int npairs, i
     if (fft_threads(max_len) == kFftThreadsSmall)
         hipLaunchKernelGGL((k_fft_pass<T, kFftThreadsSmall>), dim3(static_cast<unsigned>(tiles)), dim3(kFftThreadsSmall),
                            lds, st, pairs, prefix, npairs, pass, static_cast<cplx<T> *>(ws),
-                           static_cast<const cplx<T> *>(tw), pc, lds_elems, T(sign));
+                           static_cast<const cplx<T> *>(tw), pc, occ, lds_elems, T(sign));
     else
         hipLaunchKernelGGL((k_fft_pass<T, kFftThreads>), dim3(static_cast<unsigned>(tiles)), dim3(kFftThreads), lds, st,
                            pairs, prefix, npairs, pass, static_cast<cplx<T> *>(ws), static_cast<const cplx<T> *>(tw),
-                           pc, lds_elems, T(sign));
+                           pc, occ, lds_elems, T(sign));
     return hipGetLastError();
 }
 
@@ -1056,9 +1073,9 @@ template hipError_t launch_spread<float>(const PairDev *, const SpreadTile *, in
 template hipError_t launch_spread<double>(const PairDev *, const SpreadTile *, int64_t, const int32_t *,
                                          const void *, void *, int, double, hipStream_t);
 template hipError_t launch_fft<float>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,
-                                      const void *, int, int, double, hipStream_t);
+                                      const void *, const uint32_t *, int, int, double, hipStream_t);
 template hipError_t launch_fft<double>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,
-                                       const void *, int, int, double, hipStream_t);
+                                       const void *, const uint32_t *, int, int, double, hipStream_t);
 template hipError_t launch_transpose<float>(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
 template hipError_t launch_transpose<double>(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
 template hipError_t launch_interp<float>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,

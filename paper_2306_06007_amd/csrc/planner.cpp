@@ -757,13 +757,17 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
             // gather + pre-phase: coordinates, permutation, input value read, staged source written
             const double staged = p.dtype == HVOX_F64 ? sizeof(StagedSrc<double>) : sizeof(StagedSrc<float>);
             dp->alg_bytes[HVOX_K_PREPHASE] += pd.src_cnt * (24.0 + 4.0 + delta + staged);
-            // spreading: tile record and staged source per source, grid 1 written once
-            dp->alg_bytes[HVOX_K_SPREAD] += pd.src_cnt * (4.0 + staged) + delta * static_cast<double>(g.g1);
+            // spreading (with the gather of A5): a source's coordinates (16 bytes) and value, and
+            // every grid-1 cell its kernel touches written once, delta min(G1, N_s w^3)
+            dp->alg_bytes[HVOX_K_SPREAD] += pd.src_cnt * (16.0 + delta) +
+                                            delta * std::min(static_cast<double>(g.g1), pd.src_cnt * w3);
             dp->alg_bytes[HVOX_K_FFT_X] += delta * (static_cast<double>(g.g1) + g.bx);
             dp->alg_bytes[HVOX_K_TRANSPOSE] += delta * 2.0 * static_cast<double>(g.bx);
             dp->alg_bytes[HVOX_K_FFT_Y] += delta * (static_cast<double>(g.bx) + g.cy);
             dp->alg_bytes[HVOX_K_FFT_Z] += delta * (static_cast<double>(g.cy) + g.dz);
-            dp->alg_bytes[HVOX_K_INTERP] += pd.tgt_cnt * (24.0 + 8.0 + 16.0) +
+            // interpolation: a target's coordinates (16 bytes) and result, and every grid cell
+            // its kernel reads once, delta min(G2 window, N_t w2^3)
+            dp->alg_bytes[HVOX_K_INTERP] += pd.tgt_cnt * (16.0 + delta) +
                                             delta * std::min(static_cast<double>(g.dz), pd.tgt_cnt * w23);
             dp->alg_flops[HVOX_K_SPREAD] += pd.src_cnt * w3;
             dp->alg_flops[HVOX_K_INTERP] += pd.tgt_cnt * w23;
@@ -774,7 +778,7 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
         k = k1;
     }
     dp->alg_bytes[HVOX_K_FINAL] = tgt.n * (16.0 + 4.0 + delta);
-    dp->alg_bytes[HVOX_K_ZERO] = 16.0 * tgt.n;   // accumulator clear (grid-1 fills of sparse batches added at binning)
+    dp->alg_bytes[HVOX_K_ZERO] = 16.0 * tgt.n;   // accumulator clear
 }
 
 }  // namespace
@@ -814,6 +818,7 @@ int64_t device_bytes_bound(const HostPlan &hp)
         b += 4 * std::max<int64_t>(records, 1);
         b += static_cast<int64_t>(sizeof(SpreadTile)) * (dp->tiles_total + records / kSpreadSplit + 1);
         temp = std::max(temp, 12 * dp->tiles_total);                            // binning counts + cursors
+        b += 4 * ((dp->tiles_total + 31) / 32 + kOccWords);                     // tile occupancy bits
     }
     b += staged * max_pts;
     b += delta * hp.ws_elems;

@@ -73,7 +73,9 @@ class HvoxPlanInfo(ctypes.Structure):
                 ("grid_cells", ctypes.c_double), ("direct_terms", ctypes.c_double),
                 ("est_seconds", ctypes.c_double), ("plan_seconds", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("flags", ctypes.c_int32), ("on_device", ctypes.c_int32),
-                ("n_direct_layers", ctypes.c_int64), ("noalloc_scratch_bytes", ctypes.c_int64)]
+                ("n_direct_layers", ctypes.c_int64), ("noalloc_scratch_bytes", ctypes.c_int64),
+                ("occ_tiles", ctypes.c_int64 * 2), ("occ_xlines", ctypes.c_int64 * 2),
+                ("occ_zplanes", ctypes.c_int64 * 2)]
 
 
 class HvoxStats(ctypes.Structure):
@@ -371,8 +373,8 @@ class Plan:
         inf = HvoxPlanInfo()
         _check(self._lib.hvox_plan_info(self._plan, ctypes.byref(inf)))
         d = {name: getattr(inf, name) for name, _ in HvoxPlanInfo._fields_}
-        d["h"] = list(inf.h)
-        d["eta"] = list(inf.eta)
+        for k in ("h", "eta", "occ_tiles", "occ_xlines", "occ_zplanes"):
+            d[k] = list(getattr(inf, k))
         return d
 
     def permutation(self):

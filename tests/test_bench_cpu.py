@@ -39,14 +39,14 @@ def test_hbm_roofline_is_algorithmic_bytes_over_average_launch_time():
     assert r["traffic"] is None                   # no counter summary under that key
 
 
-def test_direct_roofline_counts_lane_operations_and_issue_cycles():
-    # 1e12 term-rows in 100 ms: 1e13 term-rows/s
+def test_direct_roofline_counts_algorithmic_operations_and_issue_cycles():
+    # 1e12 terms in 100 ms: 1e13 terms/s, 30 operations per term -> 300 TFLOP/s
     st = {"direct": {"ms": 100.0, "launches": 1, "alg_bytes": 0.0, "alg_flops": 1e12}}
+    assert bench.ALG_OPS_PER_TERM == 30.0
     for dtype in ("f32", "f64"):
         name, r = bench.roofline_entry(st, dtype, mode="no-such-mode")
         assert name == "direct" and r["bound"] == "alu" and r["unit"] == "TFLOP/s"
-        ops = bench.VALU_OPS_PER_TERM[(dtype, 1)]
-        assert r["achieved"] == pytest.approx(1e13 * ops * 2 / 1e12)
+        assert r["achieved"] == pytest.approx(300.0)
         assert r["frac"] == pytest.approx(r["achieved"] / bench.VECTOR_PEAK_TFLOPS[dtype])
         ib = r["issue_bound"]
         assert ib["term_rows_per_s"] == pytest.approx(bench.LANE_CYCLES_PER_S / bench.VALU_CYCLES_PER_TERM[(dtype, 1)])
