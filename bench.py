@@ -307,7 +307,8 @@ def main():
                          "values only for counter runs, never for the reported metric)")
     ap.add_argument("--modes", default="",
                     help="comma-separated subset of the runs reported beside the headline (forced_nufft, all_direct, "
-                         "batched_ntrans4, dense_10km, dense_10km_all_direct); default all")
+                         "batched_ntrans4, dense_10km, dense_10km_all_direct, dense_30km, sparse_100km, "
+                         "sparse_100km_forced_nufft); default all")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the runs reported beside the headline (forced NUFFT, all direct, four rows, the dense "
                          "mesh, serving)")
@@ -393,7 +394,8 @@ def main():
                                   min(1, args.warmup), dist=args.dist_runs)
     modes = {}
     wanted = set(filter(None, args.modes.split(","))) or {"forced_nufft", "all_direct", "batched_ntrans4",
-                                                           "dense_10km", "dense_10km_all_direct"}
+                                                           "dense_10km", "dense_10km_all_direct", "dense_30km",
+                                                           "sparse_100km", "sparse_100km_forced_nufft"}
     if not args.no_modes:
         # the two other execution modes of the float32 transform: every sub-problem as a
         # NUFFT (the path the spread / FFT / interp rooflines describe), every one direct
@@ -414,6 +416,22 @@ def main():
         if "dense_10km_all_direct" in wanted:
             modes["dense_10km_all_direct"] = run_mode("f32", 0.0, -1.0, 1, 0, work=dense)
         del dense
+    if not (args.no_modes or dense_head) and "dense_30km" in wanted:
+        # the 30 km rung (341k vis x 74.65M pixels)
+        dense = W.dense_dcos(30.0)
+        log(f"workload {dense.name}")
+        modes["dense_30km"] = run_mode("f32", 1e-4, args.direct_threshold, 1, 0, work=dense)
+        del dense
+    if not (args.no_modes or dense_head) and wanted & {"sparse_100km", "sparse_100km_forced_nufft"}:
+        # the sparse-mesh experiment: the 100 km rung's 394k visibilities and 500 pixels in
+        # five separate 10 x 10 patches of its DCOS grid
+        sparse = W.sparse_dcos(100.0)
+        log(f"workload {sparse.name}")
+        if "sparse_100km" in wanted:
+            modes["sparse_100km"] = run_mode("f32", 1e-4, args.direct_threshold, 5, 1, work=sparse)
+        if "sparse_100km_forced_nufft" in wanted:
+            modes["sparse_100km_forced_nufft"] = run_mode("f32", 1e-4, 0.0, 5, 1, work=sparse)
+        del sparse
     if args.lofar:
         lofar = W.lofar_like()
         log(f"workload {lofar.name}")

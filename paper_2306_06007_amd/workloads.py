@@ -242,6 +242,18 @@ DENSE_LADDER = {0.1: (273, 80), 0.3: (13_000, 160), 1.0: (95_000, 360), 3.0: (14
                 10.0: (238_000, 3200), 30.0: (341_000, 8640), 100.0: (394_000, 13_500)}
 
 
+def ladder_uvw(radius_km: float, rng: np.random.Generator, lat_deg: float = -26.82, dec_deg: float = -45.0,
+               wavelength_m: float = 2.0):
+    """Baselines of a telescope-radius rung: stations at log-radial distances
+    between 15 m and the radius, as many as three snapshots (hour angles
+    -4 h, 0, +4 h) need for the rung's visibility count."""
+    n_vis_target, _ = DENSE_LADDER[float(radius_km)]
+    n_st = max(2, int(round(0.5 + math.sqrt(0.25 + 2.0 * n_vis_target / 3.0))))
+    enu = log_radial_layout(n_st, 15.0, radius_km * 1e3, rng)
+    H = np.radians(np.linspace(-60.0, 60.0, 3))          # -4 h, 0, +4 h
+    return earth_rotation_uvw(enu, lat_deg, dec_deg, H, [wavelength_m]), n_st
+
+
 def dense_dcos(radius_km: float = 3.0, seed: int = 5, ntrans: int = 1, fov_deg: float = 30.0,
                lat_deg: float = -26.82, dec_deg: float = -45.0, wavelength_m: float = 2.0) -> Workload:
     """Dense-mesh case shaped after the paper's runtime ladder (default
@@ -254,15 +266,43 @@ def dense_dcos(radius_km: float = 3.0, seed: int = 5, ntrans: int = 1, fov_deg: 
     square DCOS grid around the phase centre; intensities U[0,1]."""
     n_vis_target, n_side = DENSE_LADDER[float(radius_km)]
     rng = np.random.default_rng(seed)
-    n_st = max(2, int(round(0.5 + math.sqrt(0.25 + 2.0 * n_vis_target / 3.0))))
-    enu = log_radial_layout(n_st, 15.0, radius_km * 1e3, rng)
-    H = np.radians(np.linspace(-60.0, 60.0, 3))          # -4 h, 0, +4 h
-    uvw = earth_rotation_uvw(enu, lat_deg, dec_deg, H, [wavelength_m])
+    uvw, n_st = ladder_uvw(radius_km, rng, lat_deg, dec_deg, wavelength_m)
     xyz = dcos_grid(n_side, fov_deg)
     sky = real_intensities(ntrans, xyz.shape[0], rng)
     vis = complex_normal(ntrans, uvw.shape[0], rng)
     return Workload(f"dense-dcos-{radius_km:g}km-{uvw.shape[0]}-vis-{xyz.shape[0]}-pix", uvw, xyz, sky, vis,
                     dict(seed=seed, radius_km=radius_km, n_stations=n_st, n_side=n_side, fov_deg=fov_deg))
+
+
+def sparse_dcos(radius_km: float = 10.0, seed: int = 7, n_regions: int = 5, side: int = 10, ntrans: int = 1,
+                fov_deg: float = 30.0) -> Workload:
+    """Sparse-mesh case shaped after the paper's sparse-sky runtime experiment:
+    the visibilities of a telescope-radius rung (as ``dense_dcos``) and only
+    500 pixels of interest -- ``n_regions`` small contiguous patches of
+    ``side`` x ``side`` pixels of that rung's 30-degree DCOS grid around
+    randomly placed calibrators (the regions are not contiguous with each
+    other), as in direction-dependent calibration.  Intensities U[0,1]."""
+    n_vis_target, n_side = DENSE_LADDER[float(radius_km)]
+    uvw, _ = ladder_uvw(radius_km, np.random.default_rng(5))     # the dense rung's baselines
+    rng = np.random.default_rng(seed)
+    # patch corners on the rung's pixel grid, kept inside the image and apart
+    corners = []
+    while len(corners) < n_regions:
+        c = rng.integers(0, n_side - side, 2)
+        if all(max(abs(int(c[0]) - a), abs(int(c[1]) - b)) >= side for a, b in corners):
+            corners.append((int(c[0]), int(c[1])))
+    # pixels (row, col) of the patches on the rung's grid (dcos_grid: col along l, row along m)
+    half = math.sin(math.radians(fov_deg) / 2.0)
+    g = np.linspace(-half, half, n_side)
+    rows = np.concatenate([np.repeat(r0 + np.arange(side), side) for r0, _ in corners])
+    cols = np.concatenate([np.tile(c0 + np.arange(side), side) for _, c0 in corners])
+    l, m = g[cols], g[rows]
+    xyz = np.stack([l, m, np.sqrt(np.maximum(0.0, 1.0 - l * l - m * m))], axis=1)
+    sky = real_intensities(ntrans, xyz.shape[0], rng)
+    vis = complex_normal(ntrans, uvw.shape[0], rng)
+    return Workload(f"sparse-dcos-{radius_km:g}km-{uvw.shape[0]}-vis-{xyz.shape[0]}-pix", uvw, xyz, sky, vis,
+                    dict(seed=seed, radius_km=radius_km, n_regions=n_regions, side=side, n_side=n_side,
+                         corners=corners, fov_deg=fov_deg))
 
 
 @dataclass

@@ -370,6 +370,37 @@ def test_dense_dcos_forced_nufft_sampled():
     assert es <= 1e-4 and ea <= 1e-4
 
 
+
+# ---- sparse skies of the paper's sparse-mesh experiment: 500 pixels in five patches -------
+@pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
+@pytest.mark.parametrize("radius_km,thr", [(3.0, -1.0), (100.0, -1.0), (100.0, 0.0)])
+def test_sparse_dcos_sky(radius_km, thr, dtype, eps):
+    """Analysis and synthesis on a 500-pixel sparse sky (five 10 x 10 patches of
+    the rung's DCOS grid) against the oracle on every output (all 500 pixels,
+    every visibility), with the automatic choice and with every sub-problem a
+    NUFFT."""
+    wl = W.sparse_dcos(radius_km)
+    es, ea, info = both_directions(wl.uvw, wl.xyz, wl.sky, wl.vis, eps, dtype, direct_threshold=thr)
+    _report(f"sparse {radius_km:g} km thr={thr:g} {dtype} {eps:g}", es, ea, info)
+    if thr == 0.0:
+        assert info["n_pairs_direct"] == 0
+    assert es <= eps and ea <= eps
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
+def test_dense_dcos_30km_sampled(dtype, eps):
+    """The 30 km rung of the paper's ladder: 340,578 vis x 74,649,600 pix."""
+    wl = W.dense_dcos(30.0)
+    rv = W.sample_rows(wl.n_vis, 256, seed=45)
+    rp = W.sample_rows(wl.n_pix, 1024, seed=46)
+    es, ea, info = both_directions(wl.uvw, wl.xyz, wl.sky, wl.vis, eps, dtype, rows_vis=rv, rows_pix=rp)
+    _report(f"dense 30 km {dtype} {eps:g}", es, ea, info)
+    assert info["n_pairs_nufft"] > 0
+    assert es <= eps and ea <= eps
+
+
 def test_zz_element_wise_summary():
     """Print the element-wise errors of every case above (largest first)."""
     for tag, es, ea, ms, ma in sorted(ELEM_LOG, key=lambda r: -max(r[3] / max(r[1], 1e-300),

@@ -337,3 +337,27 @@ def test_deterministic_plan_orders_its_work():
     assert b["n_batches"] >= a["n_batches"]
     if a["n_pairs_direct"]:
         assert a["n_direct_layers"] == 1 and b["n_direct_layers"] >= 1
+
+
+@pytest.mark.parametrize("radius_km", [0.1, 10.0, 100.0])
+def test_sparse_dcos_sky_is_500_pixels_of_the_rung_grid(radius_km):
+    """The sparse-sky case of the paper's sparse-mesh experiment: the rung's
+    baselines and 500 pixels in five separate 10 x 10 patches of its DCOS grid;
+    its host plan covers every term."""
+    wl = W.sparse_dcos(radius_km)
+    n_vis, n_side = W.DENSE_LADDER[radius_km]
+    assert wl.n_pix == 500 and abs(wl.n_vis - n_vis) <= 0.01 * n_vis + 3
+    assert np.allclose(np.linalg.norm(wl.xyz, axis=1), 1.0)
+    half = math.sin(math.radians(30.0) / 2.0)
+    step = 2 * half / (n_side - 1)
+    # every pixel sits on the rung's grid
+    assert np.allclose(np.round((wl.xyz[:, :2] + half) / step) * step - half, wl.xyz[:, :2], atol=1e-12)
+    # five patches, pairwise apart
+    corners = wl.info["corners"]
+    assert len(corners) == 5
+    for a in range(5):
+        for b in range(a + 1, 5):
+            assert max(abs(corners[a][0] - corners[b][0]), abs(corners[a][1] - corners[b][1])) >= 10
+    with hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True) as p:
+        info = p.info()
+    assert info["n_pairs_nufft"] + info["n_pairs_direct"] == info["n_vis_chunks"] * info["n_sky_chunks"]
