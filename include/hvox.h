@@ -241,6 +241,31 @@ int hvox_analysis(hvox_plan_t plan, const void *vis, void *sky, int32_t ntrans, 
 int hvox_transform_noalloc(hvox_plan_t plan, int32_t direction, const void *in, void *out, int32_t ntrans,
                            void *stream);
 
+/* Direction-dependent effects: beam shapes and DDEs, which the paper sets
+ * aside in Sect. 2 (its measurement equation omits antenna beams) and names
+ * as future work (Sect. 6).  Visibility k sees the sky through a gain
+ * A_k(r) given in separable (low-rank) form over n_terms terms,
+ *   A_k(r_n) = sum_t a[t][k] b[t][n],
+ * e.g. a time-variable primary beam (a[t][k] = 1 when visibility k belongs
+ * to snapshot t, b[t] the beam of that snapshot on the sky points) or a
+ * low-rank expansion of per-station beams.
+ *   hvox_synthesis_dde:  vis[r][k] = sum_n A_k(r_n) sky[r][n] exp(-2 pi i <p_k, r_n>)
+ *   hvox_analysis_dde:   sky[r][n] = sum_k conj(A_k(r_n)) vis[r][k] exp(+2 pi i <p_k, r_n>)
+ * (an adjoint pair).  Evaluated as n_terms rows of the plan's transform:
+ * synthesis of the rows b[t] * sky[r], combined as sum_t a[t] * (row t);
+ * analysis of the rows conj(a[t]) * vis[r], combined as sum_t conj(b[t]) *
+ * (row t), float64 accumulation.  a: device [n_terms][n_vis], b: device
+ * [n_terms][n_pix], complex of the plan's precision, in the data order of the
+ * plan (user order, or chunk order with HVOX_PREORDERED).  work: caller's
+ * device buffer of at least 2 * n_terms * max(n_vis, n_pix) complex values.
+ * sky / vis as for hvox_synthesis (ntrans rows).  HVOX_REAL_SKY applies to
+ * the combined analysis output.  HVOX_ERR_ARG for NULL pointers or
+ * n_terms < 1. */
+int hvox_synthesis_dde(hvox_plan_t plan, const void *sky, void *vis, const void *a, const void *b, int32_t n_terms,
+                       int32_t ntrans, void *work, void *stream);
+int hvox_analysis_dde(hvox_plan_t plan, const void *vis, void *sky, const void *a, const void *b, int32_t n_terms,
+                      int32_t ntrans, void *work, void *stream);
+
 /* Release every resource of the plan (device memory after synchronising the
  * plan's last stream).  NULL is a no-op. */
 int hvox_free(hvox_plan_t plan);

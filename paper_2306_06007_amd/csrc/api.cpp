@@ -44,6 +44,10 @@ hipError_t launch_direct(const DirectItem *, int64_t, const double *, int64_t, c
                          const int32_t *, const void *, int64_t, double *, int64_t, int, double, int, hipStream_t);
 template <typename T>
 hipError_t launch_finalize(const double *, int64_t, const int32_t *, void *, int, hipStream_t);
+template <typename T>
+hipError_t launch_dde_scale(const void *, const void *, void *, int64_t, int, int, hipStream_t);
+template <typename T>
+hipError_t launch_dde_combine(const void *, const void *, void *, int64_t, int, int, int, hipStream_t);
 
 namespace {
 
@@ -245,7 +249,7 @@ struct Scratch {
 // ---- executor -----------------------------------------------------------------
 template <typename T>
 int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, int32_t ntrans, hipStream_t st,
-                  const Scratch &sc, bool may_time)
+                  const Scratch &sc, bool may_time, bool allow_real = true)
 {
     const HostPlan &hp = pl->hp;
     const Params &p = hp.prm;
@@ -260,7 +264,7 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
     const int32_t *sperm = pre ? nullptr : (synthesis ? pl->sky_perm : pl->vis_perm);
     const int32_t *tperm = pre ? nullptr : (synthesis ? pl->vis_perm : pl->sky_perm);
     const double iota = synthesis ? -1.0 : 1.0;
-    const int real_only = (!synthesis && (p.flags & HVOX_REAL_SKY)) ? 1 : 0;
+    const int real_only = (allow_real && !synthesis && (p.flags & HVOX_REAL_SKY)) ? 1 : 0;
     const int det = p.deterministic() ? 1 : 0;
     using C = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
     hipError_t e = hipSuccess;
@@ -356,6 +360,55 @@ int transform(hvox_plan_s *pl, bool synthesis, const void *in, void *out, int32_
     const Scratch sc{pl->ws, pl->stage, pl->acc};
     if (pl->hp.prm.dtype == HVOX_F64) return run_direction<double>(pl, synthesis, in, out, ntrans, st, sc, true);
     return run_direction<float>(pl, synthesis, in, out, ntrans, st, sc, true);
+}
+
+// Direction-dependent gains A_k(r_n) = sum_t a[t][k] b[t][n]: per data row, the
+// n_terms rows of the transform's input (gain-weighted), one transform of
+// n_terms rows, and the gain-weighted sum of its output rows.
+template <typename T>
+int run_dde(hvox_plan_s *pl, bool synthesis, const void *in, void *out, const void *a, const void *b, int32_t terms,
+            int32_t ntrans, void *work, hipStream_t st)
+{
+    const HostPlan &hp = pl->hp;
+    const int64_t n_in = synthesis ? hp.n_pix : hp.n_vis, n_out = synthesis ? hp.n_vis : hp.n_pix;
+    // synthesis: rows b[t] * sky, combined with a[t]; analysis: rows conj(a[t]) * vis, combined with conj(b[t])
+    const void *w_in = synthesis ? b : a, *w_out = synthesis ? a : b;
+    const int conj = synthesis ? 0 : 1;
+    const int real_only = (!synthesis && (hp.prm.flags & HVOX_REAL_SKY)) ? 1 : 0;
+    using C = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+    C *X = static_cast<C *>(work);
+    C *Y = X + static_cast<int64_t>(terms) * std::max(hp.n_vis, hp.n_pix);
+    const Scratch sc{pl->ws, pl->stage, pl->acc};
+    for (int32_t r = 0; r < ntrans; ++r) {
+        const C *x_r = static_cast<const C *>(in) + static_cast<int64_t>(r) * n_in;
+        C *y_r = static_cast<C *>(out) + static_cast<int64_t>(r) * n_out;
+        hipError_t e = launch_dde_scale<T>(w_in, x_r, X, n_in, terms, conj, st);
+        if (e != hipSuccess) return fail(HVOX_ERR_HIP, std::string("HIP: ") + hipGetErrorString(e));
+        const int rc = run_direction<T>(pl, synthesis, X, Y, terms, st, sc, true, false);
+        if (rc) return rc;
+        e = launch_dde_combine<T>(w_out, Y, y_r, n_out, terms, conj, real_only, st);
+        if (e != hipSuccess) return fail(HVOX_ERR_HIP, std::string("HIP: ") + hipGetErrorString(e));
+    }
+    return HVOX_OK;
+}
+
+int transform_dde(hvox_plan_s *pl, bool synthesis, const void *in, void *out, const void *a, const void *b,
+                  int32_t terms, int32_t ntrans, void *work, void *stream)
+{
+    if (!pl) return fail(HVOX_ERR_STATE, "NULL plan");
+    if (pl->host_only) return fail(HVOX_ERR_STATE, "host-only plan cannot run transforms (hvox_plan_upload first)");
+    if (ntrans < 1 || terms < 1) return fail(HVOX_ERR_ARG, "ntrans and n_terms must be >= 1");
+    const int64_t n_in = synthesis ? pl->hp.n_pix : pl->hp.n_vis;
+    const int64_t n_out = synthesis ? pl->hp.n_vis : pl->hp.n_pix;
+    if ((n_in > 0 && !in) || (n_out > 0 && !out)) return fail(HVOX_ERR_ARG, "NULL data pointer");
+    if ((pl->hp.n_vis > 0 && !a) || (pl->hp.n_pix > 0 && !b) || !work)
+        return fail(HVOX_ERR_ARG, "NULL gain or work pointer");
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(HVOX_ERR_HIP, "hipGetDevice failed");
+    if (cur != pl->device) return fail(HVOX_ERR_STATE, "the plan's device is not the current device");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (pl->hp.prm.dtype == HVOX_F64) return run_dde<double>(pl, synthesis, in, out, a, b, terms, ntrans, work, st);
+    return run_dde<float>(pl, synthesis, in, out, a, b, terms, ntrans, work, st);
 }
 
 int upload_dir(hvox_plan_s *pl, const DirPlan &dp, DevDir *dd, hipStream_t st)
@@ -925,6 +978,26 @@ int hvox_plan_upload(hvox_plan_t plan, void *stream)
     plan->hp.prm.flags &= ~HVOX_PLAN_HOST_ONLY;
     plan->plan_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return HVOX_OK;
+}
+
+int hvox_synthesis_dde(hvox_plan_t plan, const void *sky, void *vis, const void *a, const void *b, int32_t n_terms,
+                       int32_t ntrans, void *work, void *stream)
+{
+    try {
+        return transform_dde(plan, true, sky, vis, a, b, n_terms, ntrans, work, stream);
+    } catch (...) {
+        return fail(HVOX_ERR_HIP, "unexpected failure in hvox_synthesis_dde");
+    }
+}
+
+int hvox_analysis_dde(hvox_plan_t plan, const void *vis, void *sky, const void *a, const void *b, int32_t n_terms,
+                      int32_t ntrans, void *work, void *stream)
+{
+    try {
+        return transform_dde(plan, false, vis, sky, a, b, n_terms, ntrans, work, stream);
+    } catch (...) {
+        return fail(HVOX_ERR_HIP, "unexpected failure in hvox_analysis_dde");
+    }
 }
 
 int hvox_transform_noalloc(hvox_plan_t plan, int32_t direction, const void *in, void *out, int32_t ntrans,

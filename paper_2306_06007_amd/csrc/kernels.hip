@@ -910,6 +910,42 @@ __global__ void k_finalize(const double *__restrict__ acc, int64_t n, const int3
 }
 
 // ---------------------------------------------------------------------------
+// direction-dependent gains in separable form A_k(r_n) = sum_t a[t][k] b[t][n]:
+// the rows a transform takes (scale) and the sum of the transformed rows
+// (combine).  out[t][i] = w'[t][i] x[i] and out[i] = sum_t w'[t][i] y[t][i],
+// w' = w or conj(w); the combination accumulates in float64.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_dde_scale(const cplx<T> *__restrict__ w, const cplx<T> *__restrict__ x, cplx<T> *__restrict__ out,
+                            int64_t n, int terms, int conj_w)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const cplx<T> v = x[i];
+    for (int t = 0; t < terms; ++t) {
+        cplx<T> g = w[(int64_t)t * n + i];
+        if (conj_w) g.y = -g.y;
+        out[(int64_t)t * n + i] = cmul<T>(g, v);
+    }
+}
+
+template <typename T>
+__global__ void k_dde_combine(const cplx<T> *__restrict__ w, const cplx<T> *__restrict__ y, cplx<T> *__restrict__ out,
+                              int64_t n, int terms, int conj_w, int real_only)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double re = 0.0, im = 0.0;
+    for (int t = 0; t < terms; ++t) {
+        const cplx<T> g = w[(int64_t)t * n + i], v = y[(int64_t)t * n + i];
+        const double gi = conj_w ? -(double)g.y : (double)g.y;
+        re += (double)g.x * v.x - gi * v.y;
+        im += (double)g.x * v.y + gi * v.x;
+    }
+    out[i] = mk<T>(T(re), real_only ? T(0) : T(im));
+}
+
+// ---------------------------------------------------------------------------
 // launch wrappers (host)
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(int64_t n, int per, int64_t cap)
@@ -1089,6 +1125,32 @@ template hipError_t launch_direct<float>(const DirectItem *, int64_t, const doub
 template hipError_t launch_direct<double>(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
                                           const int32_t *, const void *, int64_t, double *, int64_t, int, double, int,
                                           hipStream_t);
+template <typename T>
+hipError_t launch_dde_scale(const void *w, const void *x, void *out, int64_t n, int terms, int conj_w, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dde_scale<T>, dim3(blocks_for(n, 256, INT32_MAX)), dim3(256), 0, st,
+                       static_cast<const cplx<T> *>(w), static_cast<const cplx<T> *>(x), static_cast<cplx<T> *>(out), n,
+                       terms, conj_w);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dde_combine(const void *w, const void *y, void *out, int64_t n, int terms, int conj_w, int real_only,
+                              hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dde_combine<T>, dim3(blocks_for(n, 256, INT32_MAX)), dim3(256), 0, st,
+                       static_cast<const cplx<T> *>(w), static_cast<const cplx<T> *>(y), static_cast<cplx<T> *>(out), n,
+                       terms, conj_w, real_only);
+    return hipGetLastError();
+}
+
+template hipError_t launch_dde_scale<float>(const void *, const void *, void *, int64_t, int, int, hipStream_t);
+template hipError_t launch_dde_scale<double>(const void *, const void *, void *, int64_t, int, int, hipStream_t);
+template hipError_t launch_dde_combine<float>(const void *, const void *, void *, int64_t, int, int, int, hipStream_t);
+template hipError_t launch_dde_combine<double>(const void *, const void *, void *, int64_t, int, int, int,
+                                               hipStream_t);
 template hipError_t launch_finalize<float>(const double *, int64_t, const int32_t *, void *, int, hipStream_t);
 template hipError_t launch_finalize<double>(const double *, int64_t, const int32_t *, void *, int, hipStream_t);
 

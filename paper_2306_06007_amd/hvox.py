@@ -83,7 +83,8 @@ class HvoxStats(ctypes.Structure):
                 ("alg_bytes", ctypes.c_double * len(KERNELS)), ("alg_flops", ctypes.c_double * len(KERNELS))]
 
 
-EXPORTS = ("hvox_plan", "hvox_plan_upload", "hvox_synthesis", "hvox_transform_noalloc", "hvox_analysis", "hvox_free", "hvox_plan_info",
+EXPORTS = ("hvox_plan", "hvox_plan_upload", "hvox_synthesis", "hvox_transform_noalloc", "hvox_synthesis_dde",
+           "hvox_analysis_dde", "hvox_analysis", "hvox_free", "hvox_plan_info",
            "hvox_plan_permutation", "hvox_plan_chunks", "hvox_stats", "hvox_stats_reset", "hvox_set_timing",
            "hvox_kernel_params", "hvox_alg1", "hvox_partition", "hvox_error_string",
            "hvox_last_error", "hvox_version")
@@ -110,6 +111,10 @@ def load_library():
         f = getattr(lib, name)
         f.restype = ctypes.c_int
         f.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
+    for name in ("hvox_synthesis_dde", "hvox_analysis_dde"):
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
     lib.hvox_transform_noalloc.restype = ctypes.c_int
     lib.hvox_transform_noalloc.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, vp]
     lib.hvox_plan_upload.restype = ctypes.c_int
@@ -368,6 +373,43 @@ class Plan:
         self.device = torch.device("cuda", torch.cuda.current_device())
         _check(self._lib.hvox_plan_upload(self._plan, ctypes.c_void_p(self._stream_handle(stream))))
         self.host_only = False
+
+    def _gains(self, a, b):
+        ta, _ = self._prep(a, self.n_vis, "a")
+        tb, _ = self._prep(b, self.n_pix, "b")
+        if ta.shape[0] != tb.shape[0]:
+            raise ValueError("a and b must hold the same number of terms")
+        return ta, tb
+
+    def synthesis_dde(self, sky, a, b, out=None, stream=None):
+        """Synthesis through direction-dependent gains A_k(r_n) = sum_t a[t, k] b[t, n]:
+        V[r, k] = sum_n A_k(r_n) sky[r, n] exp(-2 pi i <p_k, r_n>).  a: (n_terms, n_vis),
+        b: (n_terms, n_pix) complex tensors on the plan's GPU."""
+        torch = _torch()
+        self._check_runnable()
+        x, squeeze = self._prep(sky, self.n_pix, "sky")
+        ta, tb = self._gains(a, b)
+        y = self._out(x.shape[0], self.n_vis, out)
+        work = torch.empty((2, ta.shape[0], max(self.n_vis, self.n_pix)), dtype=self.complex_dtype, device=self.device)
+        _check(self._lib.hvox_synthesis_dde(self._plan, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                            ctypes.c_void_p(ta.data_ptr()), ctypes.c_void_p(tb.data_ptr()),
+                                            ta.shape[0], x.shape[0], ctypes.c_void_p(work.data_ptr()),
+                                            ctypes.c_void_p(self._stream_handle(stream))))
+        return y[0] if squeeze and out is None else y
+
+    def analysis_dde(self, vis, a, b, out=None, stream=None):
+        """The adjoint: I[r, n] = sum_k conj(A_k(r_n)) vis[r, k] exp(+2 pi i <p_k, r_n>)."""
+        torch = _torch()
+        self._check_runnable()
+        x, squeeze = self._prep(vis, self.n_vis, "vis")
+        ta, tb = self._gains(a, b)
+        y = self._out(x.shape[0], self.n_pix, out)
+        work = torch.empty((2, ta.shape[0], max(self.n_vis, self.n_pix)), dtype=self.complex_dtype, device=self.device)
+        _check(self._lib.hvox_analysis_dde(self._plan, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                           ctypes.c_void_p(ta.data_ptr()), ctypes.c_void_p(tb.data_ptr()),
+                                           ta.shape[0], x.shape[0], ctypes.c_void_p(work.data_ptr()),
+                                           ctypes.c_void_p(self._stream_handle(stream))))
+        return y[0] if squeeze and out is None else y
 
     def info(self) -> dict:
         inf = HvoxPlanInfo()

@@ -348,6 +348,28 @@ def serving_requests(seed: int = 4, n_req: int = 64, mean_gap_s: float = 0.010,
     return out
 
 
+def snapshot_beams(n_vis: int, n_times: int, xyz: np.ndarray, fwhm_deg: float = 8.0,
+                   drift_deg: float = 3.0) -> tuple[np.ndarray, np.ndarray]:
+    """Direction-dependent gains of a time-variable primary beam in the
+    separable form A_k(r_n) = sum_t a[t, k] b[t, n]: visibility k belongs to
+    snapshot t = k // (n_vis / n_times) (the [hour angle][pair] order of
+    earth_rotation_uvw) and sees b[t], a Gaussian beam of the given FWHM whose
+    pointing drifts linearly by drift_deg in x across the observation.
+    a: (n_times, n_vis) 0/1, b: (n_times, n_pix) real, both complex128."""
+    per = n_vis // n_times
+    if per * n_times != n_vis:
+        raise ValueError("n_vis must be a multiple of n_times")
+    a = np.zeros((n_times, n_vis), dtype=np.complex128)
+    for t in range(n_times):
+        a[t, t * per:(t + 1) * per] = 1.0
+    s = math.radians(fwhm_deg) / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    off = np.radians(np.linspace(-0.5 * drift_deg, 0.5 * drift_deg, n_times))
+    centres = np.stack([np.sin(off), np.zeros(n_times), np.cos(off)], axis=1)
+    d2 = ((xyz[None, :, :] - centres[:, None, :]) ** 2).sum(-1)
+    b = np.exp(-d2 / (2.0 * s * s)).astype(np.complex128)
+    return a, b
+
+
 def noise_for_snr(signal_power_sum: float, m: int, snr_db: float,
                   rng: np.random.Generator) -> np.ndarray:
     """Complex Gaussian noise n ~ CN(0, s2) of length m with

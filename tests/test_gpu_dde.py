@@ -1,0 +1,91 @@
+"""Direction-dependent gains on the GPU (hvox_synthesis_dde / hvox_analysis_dde):
+against the oracle's dense DDE sums on small inputs (every output), against
+its row-sampled form on a time-variable primary beam over an SKA-like layout,
+the adjoint identity, and the unit gain reducing to the plain transforms."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dde
+import paper_2306_06007_amd as hv
+from paper_2306_06007_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _t(a, dtype):
+    import torch
+    cd = torch.complex128 if dtype == "f64" else torch.complex64
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=cd)
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+@pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
+@pytest.mark.parametrize("thr", [-1.0, 0.0])
+def test_dde_small_against_dense_oracle(dtype, eps, thr):
+    rng = np.random.default_rng(21)
+    wl = W.compact_disk(n_vis=900, n_pix=1100, ntrans=2)
+    terms = 3
+    a = rng.normal(size=(terms, wl.n_vis)) + 1j * rng.normal(size=(terms, wl.n_vis))
+    b = rng.normal(size=(terms, wl.n_pix)) + 1j * rng.normal(size=(terms, wl.n_pix))
+    with hv.Plan(wl.uvw, wl.xyz, eps, dtype, direct_threshold=thr, max_fft_bytes=4e6) as p:
+        V = _np(p.synthesis_dde(_t(wl.sky, dtype), _t(a, dtype), _t(b, dtype)))
+        I = _np(p.analysis_dde(_t(wl.vis, dtype), _t(a, dtype), _t(b, dtype)))
+    Vref = dde.synthesis_dense(wl.uvw, wl.xyz, wl.sky, a, b)
+    Iref = dde.analysis_dense(wl.uvw, wl.xyz, wl.vis, a, b)
+    es, ea = oracle.rel_l2(V, Vref), oracle.rel_l2(I, Iref)
+    ms, ma = oracle.max_rel_err(V, Vref), oracle.max_rel_err(I, Iref)
+    print(f"[dde {dtype} thr={thr}] syn {es:.2e} (max {ms:.2e}) ana {ea:.2e} (max {ma:.2e})", flush=True)
+    assert es <= eps and ea <= eps
+    assert ms <= 5 * eps and ma <= 5 * eps
+
+
+@pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
+def test_time_variable_primary_beam(dtype, eps):
+    """SKA-like snapshots, each seen through its own drifting Gaussian beam."""
+    n_times = 6
+    uvw = W.ska_like_uvw(n_ant=60, n_times=n_times)
+    xyz = W.fibonacci_cap(40000, 10.0)
+    rng = np.random.default_rng(4)
+    sky = W.real_intensities(1, xyz.shape[0], rng)
+    vis = W.complex_normal(1, uvw.shape[0], rng)
+    a, b = W.snapshot_beams(uvw.shape[0], n_times, xyz)
+    rv = W.sample_rows(uvw.shape[0], 1024, seed=7)
+    rp = W.sample_rows(xyz.shape[0], 1024, seed=8)
+    with hv.Plan(uvw, xyz, eps, dtype, max_fft_bytes=64e6) as p:
+        V = _np(p.synthesis_dde(_t(sky, dtype), _t(a, dtype), _t(b, dtype)))
+        I = _np(p.analysis_dde(_t(vis, dtype), _t(a, dtype), _t(b, dtype)))
+    es = oracle.rel_l2(V[:, rv], dde.synthesis_rows(uvw, xyz, sky, a, b, rv))
+    ea = oracle.rel_l2(I[:, rp], dde.analysis_rows(uvw, xyz, vis, a, b, rp))
+    print(f"[beam {dtype}] syn {es:.2e} ana {ea:.2e}", flush=True)
+    assert es <= eps and ea <= eps
+
+
+def test_dde_adjoint_and_unit_gain():
+    rng = np.random.default_rng(5)
+    wl = W.ska_like(n_pix=15000, n_ant=40, n_times=8)
+    x = W.complex_normal(1, wl.n_pix, rng)
+    y = W.complex_normal(1, wl.n_vis, rng)
+    a = rng.normal(size=(2, wl.n_vis)) + 1j * rng.normal(size=(2, wl.n_vis))
+    b = rng.normal(size=(2, wl.n_pix)) + 1j * rng.normal(size=(2, wl.n_pix))
+    for dtype, eps in (("f64", 1e-9), ("f32", 1e-4)):
+        with hv.Plan(wl.uvw, wl.xyz, eps, dtype, max_fft_bytes=16e6) as p:
+            Ax = _np(p.synthesis_dde(_t(x, dtype), _t(a, dtype), _t(b, dtype)))
+            AHy = _np(p.analysis_dde(_t(y, dtype), _t(a, dtype), _t(b, dtype)))
+            # a unit gain is the plain transform
+            one_v, one_p = np.ones((1, wl.n_vis)), np.ones((1, wl.n_pix))
+            V1 = _np(p.synthesis_dde(_t(x, dtype), _t(one_v, dtype), _t(one_p, dtype)))
+            V0 = _np(p.synthesis(_t(x, dtype)))
+        assert oracle.rel_l2(V1, V0) <= (1e-14 if dtype == "f64" else 1e-6)
+        scale = np.linalg.norm(Ax) * np.linalg.norm(y)
+        assert abs(np.vdot(y, Ax) - np.vdot(AHy, x)) <= 2 * eps * scale
