@@ -41,7 +41,8 @@ hipError_t launch_interp(const PairDev *, const int64_t *, int, int64_t, const d
                          const void *, double *, int, double, double, int, hipStream_t);
 template <typename T>
 hipError_t launch_direct(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
-                         const int32_t *, const void *, int64_t, double *, int64_t, int, double, int, hipStream_t);
+                         const int32_t *, const void *, int64_t, double *, int64_t, int, double, int, int64_t,
+                         hipStream_t);
 template <typename T>
 hipError_t launch_finalize(const double *, int64_t, const int32_t *, void *, int, hipStream_t);
 template <typename T>
@@ -102,6 +103,12 @@ struct hvox_plan_s {
     void *stage = nullptr;                              // staged sources of one batch (value and footprint)
     double *acc = nullptr;
     hipStream_t last_stream = nullptr;
+    // a second stream (default priority) the direct sum runs on while the NUFFT
+    // batches run on the caller's stream, forked and joined with two events
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    // workgroups of a direct-sum launch beside NUFFT work (persistent grid; 0: one per item)
+    int64_t direct_grid_cap = 0;
     double plan_seconds = 0.0;
     // timing
     std::vector<hvox::TimedLaunch> pending;
@@ -165,6 +172,9 @@ hipError_t upload(hvox_plan_s *pl, const std::vector<V> &v, V **dst, hipStream_t
 
 void release(hvox_plan_s *pl)
 {
+    if (pl->side) { (void)hipStreamSynchronize(pl->side); (void)hipStreamDestroy(pl->side); pl->side = nullptr; }
+    if (pl->fork_ev) { (void)hipEventDestroy(pl->fork_ev); pl->fork_ev = nullptr; }
+    if (pl->join_ev) { (void)hipEventDestroy(pl->join_ev); pl->join_ev = nullptr; }
     for (auto &a : pl->allocations) raw_free(pl, a.first, a.second, pl->last_stream);
     pl->allocations.clear();
     pl->resident_bytes = 0;
@@ -274,6 +284,16 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
         if (e != hipSuccess) return fail(HVOX_ERR_HIP, std::string("HIP: ") + hipGetErrorString(e)); \
     } while (0)
 
+    // the direct blocks run on the plan's second stream, overlapping the NUFFT
+    // batches (VALU-bound direct sum beside memory-bound grid passes; both add
+    // into the accumulator atomically), unless the plan is deterministic (its
+    // direct layers add after the batches, in order) or the call may not
+    // create work outside the caller's stream.
+    // Calls that time every kernel (HVOX_TIMING) run serialised, so that each
+    // kernel's HIP-event time is its own and not a share of the GPU.
+    const bool overlap = may_time && !(p.flags & HVOX_TIMING) && !det && pl->side && !dp.batches.empty() &&
+                         !dp.direct.empty();
+    hipStream_t dst = overlap ? pl->side : st;
     // rows in groups of up to kRowBatch: the NUFFT sub-problems run row by row
     // into the group's accumulator rows, the direct sum covers all rows of the
     // group in one launch (its phase factors are shared by the rows)
@@ -281,6 +301,20 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
         const int nb = static_cast<int>(std::min<int32_t>(kRowBatch, ntrans - t0));
         if (n_tgt == 0) continue;
         HVOX_TRY(timed(pl, may_time, HVOX_K_ZERO, st, [&] { return launch_zero(sc.acc, 2 * n_tgt * nb, st); }));
+        if (overlap) {
+            // fork: the direct sum starts once the accumulator is clear
+            HVOX_TRY(hipEventRecord(pl->fork_ev, st));
+            HVOX_TRY(hipStreamWaitEvent(pl->side, pl->fork_ev, 0));
+            for (size_t l = 0; l + 1 < dp.direct_layer_off.size(); ++l) {
+                const int64_t i0 = dp.direct_layer_off[l], i1 = dp.direct_layer_off[l + 1];
+                HVOX_TRY(timed(pl, may_time, HVOX_K_DIRECT, dst, [&] {
+                    return launch_direct<T>(dd.direct + i0, i1 - i0, sxyz, n_src, txyz, n_tgt, sperm,
+                                            static_cast<const C *>(in) + static_cast<int64_t>(t0) * n_src, n_src,
+                                            sc.acc, 2 * n_tgt, nb, iota, det, pl->direct_grid_cap, dst);
+                }));
+            }
+            HVOX_TRY(hipEventRecord(pl->join_ev, pl->side));
+        }
         for (int r = 0; r < nb; ++r) {
             const C *in_t = static_cast<const C *>(in) + static_cast<int64_t>(t0 + r) * n_src;
             double *acc_r = sc.acc + 2 * n_tgt * r;
@@ -319,14 +353,16 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
                 }));
             }
         }
-        // direct blocks: one launch, or (deterministic plans) one launch per layer of
-        // items that share no target, in a fixed order
-        for (size_t l = 0; l + 1 < dp.direct_layer_off.size(); ++l) {
+        // direct blocks (unless already on the second stream): one launch, or
+        // (deterministic plans) one launch per layer of items that share no
+        // target, in a fixed order
+        if (overlap) HVOX_TRY(hipStreamWaitEvent(st, pl->join_ev, 0));   // join before the finalize
+        else for (size_t l = 0; l + 1 < dp.direct_layer_off.size(); ++l) {
             const int64_t i0 = dp.direct_layer_off[l], i1 = dp.direct_layer_off[l + 1];
             HVOX_TRY(timed(pl, may_time, HVOX_K_DIRECT, st, [&] {
                 return launch_direct<T>(dd.direct + i0, i1 - i0, sxyz, n_src, txyz, n_tgt, sperm,
                                         static_cast<const C *>(in) + static_cast<int64_t>(t0) * n_src, n_src, sc.acc,
-                                        2 * n_tgt, nb, iota, det, st);
+                                        2 * n_tgt, nb, iota, det, 0, st);
             }));
         }
         for (int r = 0; r < nb; ++r) {
@@ -700,6 +736,20 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
         for (const Batch &b : dp->batches) max_pts = std::max(max_pts, b.pts);
     const size_t staged = p.dtype == HVOX_F64 ? sizeof(StagedSrc<double>) : sizeof(StagedSrc<float>);
     if (max_pts > 0) chk(dev_alloc(pl, staged * static_cast<size_t>(max_pts), &pl->stage, true, st), "source staging");
+    if (rc) return bail(rc);
+    // the direct sum's stream and the fork / join events; its grid is capped at
+    // kDirectWgPerCu workgroups per CU so the NUFFT kernels find room beside it
+    // (HVOX_DIRECT_WG_PER_CU overrides the cap for tuning, 0 = uncapped)
+    {
+        int ncu = 0;
+        chk(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, pl->device), "CU count");
+        int per_cu = kDirectWgPerCu;
+        if (const char *v = std::getenv("HVOX_DIRECT_WG_PER_CU")) per_cu = std::atoi(v);
+        pl->direct_grid_cap = per_cu > 0 ? static_cast<int64_t>(per_cu) * ncu : 0;
+    }
+    chk(hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking), "direct-sum stream");
+    chk(hipEventCreateWithFlags(&pl->fork_ev, hipEventDisableTiming), "fork event");
+    chk(hipEventCreateWithFlags(&pl->join_ev, hipEventDisableTiming), "join event");
     if (rc) return bail(rc);
     chk(hipStreamSynchronize(st), "plan upload");
     return rc;

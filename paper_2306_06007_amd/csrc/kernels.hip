@@ -706,39 +706,57 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
         const int sx = P.wstart[0], sy = P.wstart[1], sz = P.wstart[2];
         const cplx<T> *grid = ws + P.bufA;          // [wx][wy][wz], z fastest
         const int xstride = wy * wz;
-        for (int e = sub; e < w * w; e += kInterpLanes) {
+        // x cells eight at a time (the offsets and weights of a chunk shared by every
+        // (y, z) row of the target); cells beyond the kernel support or outside the
+        // kept window get weight 0 and the address of a cell the target reads anyway
+        // (its last column, clamped into the window), so the loads carry no branches
+        // and fetch no line the window does not need.  Each lane takes two (y, z)
+        // rows per step, sixteen loads in flight.
+        auto column = [&](int e, T &kyz) -> const cplx<T> * {
             const int dy = e / w, dz = e - dy * w;
             int qy = m0[1] + dy - sy, qz = m0[2] + dz - sz;
             if (fy) { qy %= n2y; if (qy < 0) qy += n2y; }
             if (fz) { qz %= n2z; if (qz < 0) qz += n2z; }
             const bool ok = qy >= 0 && qy < wy && qz >= 0 && qz < wz;
-            const T kyz = ok ? ker[slot][w + dy] * ker[slot][2 * w + dz] : T(0);
-            const cplx<T> *col = grid + (ok ? qy * wz + qz : 0);
-            T sr = T(0), si = T(0);
-            // eight x cells at a time: cells beyond the kernel support or outside the
-            // kept window get weight 0 and the address of a cell the target reads
-            // anyway (its last column, clamped into the window), so the loads carry no
-            // branches, issue together and fetch no line the window does not need
-            for (int dx0 = 0; dx0 < w; dx0 += 8) {
-                cplx<T> gv[8];
-                T kx[8];
+            kyz = ok ? ker[slot][w + dy] * ker[slot][2 * w + dz] : T(0);
+            return grid + (ok ? qy * wz + qz : 0);
+        };
+        for (int dx0 = 0; dx0 < w; dx0 += 8) {
+            int64_t xo[8];
+            T kx[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int dx = min(dx0 + u, w - 1);
-                    int qx = m0[0] + dx - sx;
-                    if (fx) { qx %= n2x; if (qx < 0) qx += n2x; }
-                    const bool okx = dx0 + u < w && qx >= 0 && qx < wx;
-                    kx[u] = okx ? ker[slot][dx] : T(0);
-                    gv[u] = col[(int64_t)min(max(qx, 0), wx - 1) * xstride];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    sr += gv[u].x * kx[u];
-                    si += gv[u].y * kx[u];
-                }
+            for (int u = 0; u < 8; ++u) {
+                const int dx = min(dx0 + u, w - 1);
+                int qx = m0[0] + dx - sx;
+                if (fx) { qx %= n2x; if (qx < 0) qx += n2x; }
+                const bool okx = dx0 + u < w && qx >= 0 && qx < wx;
+                kx[u] = okx ? ker[slot][dx] : T(0);
+                xo[u] = (int64_t)min(max(qx, 0), wx - 1) * xstride;
             }
-            ar += sr * kyz;
-            ai += si * kyz;
+            for (int e0 = sub; e0 < w * w; e0 += 2 * kInterpLanes) {
+                const int e1 = e0 + kInterpLanes;
+                const bool has1 = e1 < w * w;
+                T kyz0, kyz1;
+                const cplx<T> *col0 = column(e0, kyz0);
+                const cplx<T> *col1 = column(has1 ? e1 : e0, kyz1);   // no second row: a repeat, weight 0
+                if (!has1) kyz1 = T(0);
+                cplx<T> g0[8], g1[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    g0[u] = col0[xo[u]];
+                    g1[u] = col1[xo[u]];
+                }
+                T s0r = T(0), s0i = T(0), s1r = T(0), s1i = T(0);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    s0r += g0[u].x * kx[u];
+                    s0i += g0[u].y * kx[u];
+                    s1r += g1[u].x * kx[u];
+                    s1i += g1[u].y * kx[u];
+                }
+                ar += s0r * kyz0 + s1r * kyz1;
+                ai += s0i * kyz0 + s1i * kyz1;
+            }
         }
     }
     // reduce over the target's lane group (xor offsets below the group size stay inside it)
@@ -783,18 +801,13 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
 // ---------------------------------------------------------------------------
 
 template <typename T, int NT>
-__global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__restrict__ items,
-                                                           const double *__restrict__ sxyz, int64_t nsrc,
-                                                           const double *__restrict__ txyz, int64_t ntgt,
-                                                           const int32_t *__restrict__ perm,
-                                                           const cplx<T> *__restrict__ in, int64_t in_stride,
-                                                           double *__restrict__ acc, int64_t acc_stride, double iota,
-                                                           int det)
+__device__ __forceinline__ void direct_item(const DirectItem it, const double *__restrict__ sxyz, int64_t nsrc,
+                                            const double *__restrict__ txyz, int64_t ntgt,
+                                            const int32_t *__restrict__ perm, const cplx<T> *__restrict__ in,
+                                            int64_t in_stride, double *__restrict__ acc, int64_t acc_stride,
+                                            double iota, int det, double *lx, double *ly, double *lz,
+                                            cplx<T> (*lc)[kDirectSrcTile])
 {
-    static_assert(kDirectSrcTile == kDirectThreads && kDirectTile == 2 * kDirectThreads, "direct tiling");
-    __shared__ double lx[kDirectSrcTile], ly[kDirectSrcTile], lz[kDirectSrcTile];
-    __shared__ cplx<T> lc[NT][kDirectSrcTile];
-    const DirectItem it = items[blockIdx.x];
     const int tid = threadIdx.x;
     // two targets per thread: each staged source is read from LDS once for both
     const bool has0 = tid < it.tgt_cnt, has1 = tid + kDirectThreads < it.tgt_cnt;
@@ -893,6 +906,30 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__r
                 atomicAdd(ar + 2 * k1 + 1, a1i[r]);
             }
         }
+    }
+}
+
+// One workgroup per work item, or (persistent launches, grid smaller than
+// the item count) each workgroup loops over items blockIdx.x, + gridDim.x,
+// ...: a capped grid leaves room on every CU for the kernels of the NUFFT
+// sub-problems running beside the direct sum on another stream.  Items stay
+// source-segment-major across consecutive workgroups either way.
+template <typename T, int NT>
+__global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__restrict__ items, int64_t nitems,
+                                                           const double *__restrict__ sxyz, int64_t nsrc,
+                                                           const double *__restrict__ txyz, int64_t ntgt,
+                                                           const int32_t *__restrict__ perm,
+                                                           const cplx<T> *__restrict__ in, int64_t in_stride,
+                                                           double *__restrict__ acc, int64_t acc_stride, double iota,
+                                                           int det)
+{
+    static_assert(kDirectSrcTile == kDirectThreads && kDirectTile == 2 * kDirectThreads, "direct tiling");
+    __shared__ double lx[kDirectSrcTile], ly[kDirectSrcTile], lz[kDirectSrcTile];
+    __shared__ cplx<T> lc[NT][kDirectSrcTile];
+    for (int64_t w = blockIdx.x; w < nitems; w += gridDim.x) {
+        if (w != blockIdx.x) __syncthreads();   // the previous item's last tile is read before restaging
+        direct_item<T, NT>(items[w], sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc, acc_stride, iota, det, lx, ly,
+                           lz, lc);
     }
 }
 
@@ -1056,15 +1093,23 @@ template <typename T, int NT>
 static hipError_t launch_direct_rows(const DirectItem *items, int64_t nitems, const double *sxyz, int64_t nsrc,
                                      const double *txyz, int64_t ntgt, const int32_t *perm, const void *in,
                                      int64_t in_stride, double *acc, int64_t acc_stride, double iota, int det,
-                                     hipStream_t st)
+                                     int64_t grid_cap, hipStream_t st)
 {
+    if (grid_cap > 0) {
+        // persistent: at most grid_cap workgroups looping over the items
+        const int64_t nb = std::min<int64_t>(std::min<int64_t>(grid_cap, nitems), kMaxLaunchBlocks);
+        hipLaunchKernelGGL((k_direct<T, NT>), dim3(static_cast<unsigned>(nb)), dim3(kDirectThreads), 0, st, items,
+                           nitems, sxyz, nsrc, txyz, ntgt, perm, static_cast<const cplx<T> *>(in), in_stride, acc,
+                           acc_stride, iota, det);
+        return hipGetLastError();
+    }
     // one workgroup per item, in launches of at most kMaxLaunchBlocks workgroups
     // (a dispatch counts its work-items in 32 bits)
     for (int64_t i0 = 0; i0 < nitems; i0 += kMaxLaunchBlocks) {
         const int64_t nb = std::min<int64_t>(kMaxLaunchBlocks, nitems - i0);
         hipLaunchKernelGGL((k_direct<T, NT>), dim3(static_cast<unsigned>(nb)), dim3(kDirectThreads), 0, st,
-                           items + i0, sxyz, nsrc, txyz, ntgt, perm, static_cast<const cplx<T> *>(in), in_stride, acc,
-                           acc_stride, iota, det);
+                           items + i0, nb, sxyz, nsrc, txyz, ntgt, perm, static_cast<const cplx<T> *>(in), in_stride,
+                           acc, acc_stride, iota, det);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1074,18 +1119,19 @@ static hipError_t launch_direct_rows(const DirectItem *items, int64_t nitems, co
 template <typename T>
 hipError_t launch_direct(const DirectItem *items, int64_t nitems, const double *sxyz, int64_t nsrc,
                          const double *txyz, int64_t ntgt, const int32_t *perm, const void *in, int64_t in_stride,
-                         double *acc, int64_t acc_stride, int rows, double iota, int det, hipStream_t st)
+                         double *acc, int64_t acc_stride, int rows, double iota, int det, int64_t grid_cap,
+                         hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
     switch (rows) {
     case 1: return launch_direct_rows<T, 1>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
-                                            acc_stride, iota, det, st);
+                                            acc_stride, iota, det, grid_cap, st);
     case 2: return launch_direct_rows<T, 2>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
-                                            acc_stride, iota, det, st);
+                                            acc_stride, iota, det, grid_cap, st);
     case 3: return launch_direct_rows<T, 3>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
-                                            acc_stride, iota, det, st);
+                                            acc_stride, iota, det, grid_cap, st);
     case 4: return launch_direct_rows<T, 4>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
-                                            acc_stride, iota, det, st);
+                                            acc_stride, iota, det, grid_cap, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1121,10 +1167,10 @@ template hipError_t launch_interp<double>(const PairDev *, const int64_t *, int,
                                           hipStream_t);
 template hipError_t launch_direct<float>(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
                                          const int32_t *, const void *, int64_t, double *, int64_t, int, double, int,
-                                         hipStream_t);
+                                         int64_t, hipStream_t);
 template hipError_t launch_direct<double>(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
                                           const int32_t *, const void *, int64_t, double *, int64_t, int, double, int,
-                                          hipStream_t);
+                                          int64_t, hipStream_t);
 template <typename T>
 hipError_t launch_dde_scale(const void *w, const void *x, void *out, int64_t n, int terms, int conj_w, hipStream_t st)
 {
