@@ -307,8 +307,8 @@ def main():
                          "values only for counter runs, never for the reported metric)")
     ap.add_argument("--modes", default="",
                     help="comma-separated subset of the runs reported beside the headline (forced_nufft, all_direct, "
-                         "batched_ntrans4, dense_10km, dense_10km_all_direct, dense_30km, sparse_100km, "
-                         "sparse_100km_forced_nufft); default all")
+                         "batched_ntrans4, forced_nufft_ntrans4, dense_10km, dense_10km_all_direct, dense_30km, "
+                         "sparse_100km, sparse_100km_forced_nufft); default all")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the runs reported beside the headline (forced NUFFT, all direct, four rows, the dense "
                          "mesh, serving)")
@@ -395,7 +395,8 @@ def main():
     modes = {}
     wanted = set(filter(None, args.modes.split(","))) or {"forced_nufft", "all_direct", "batched_ntrans4",
                                                            "dense_10km", "dense_10km_all_direct", "dense_30km",
-                                                           "sparse_100km", "sparse_100km_forced_nufft"}
+                                                           "sparse_100km", "sparse_100km_forced_nufft",
+                                                           "forced_nufft_ntrans4"}
     if not args.no_modes:
         # the two other execution modes of the float32 transform: every sub-problem as a
         # NUFFT (the path the spread / FFT / interp rooflines describe), every one direct
@@ -406,6 +407,9 @@ def main():
         # ntrans = 4 data rows through one plan (e.g. channels or polarisations)
         if "batched_ntrans4" in wanted:
             modes["batched_ntrans4"] = run_mode("f32", 1e-4, args.direct_threshold, 1, 1, ntrans=4)
+        # four rows through NUFFT sub-problems only (what a row costs on the NUFFT path)
+        if "forced_nufft_ntrans4" in wanted:
+            modes["forced_nufft_ntrans4"] = run_mode("f32", 1e-4, 0.0, 1, 0, ntrans=4)
     if not (args.no_modes or dense_head) and wanted & {"dense_10km", "dense_10km_all_direct"}:
         # a dense 30-degree DCOS image of the paper's telescope-radius ladder (10 km rung,
         # 238k vis x 10.24M pixels): most terms go through NUFFT sub-problems
@@ -497,7 +501,7 @@ def main():
     if modes:
         out["modes"] = {}
         for m, r in modes.items():
-            rows = 4 if m == "batched_ntrans4" else 1
+            rows = 4 if m in ("batched_ntrans4", "forced_nufft_ntrans4") else 1
             ent = {"ms_per_step": r["sec"] * 1e3, "value": rows * r["n_units"] / r["sec"], "ntrans": rows,
                    "workload": r["workload"], "dtype": r["dtype"],
                    "n_pairs_nufft": r["info"]["n_pairs_nufft"], "n_pairs_direct": r["info"]["n_pairs_direct"],

@@ -192,6 +192,24 @@ def test_ntrans_batch_equals_loop():
 
 
 @pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
+def test_ntrans_four_rows_forced_nufft(dtype, eps):
+    """Four data rows (the ntrans of Sect. 4) through NUFFT sub-problems only:
+    every row meets eps against the oracle, and equals the same row alone."""
+    wl = W.ska_like(n_pix=20000, n_ant=40, n_times=10, ntrans=4)
+    with hv.Plan(wl.uvw, wl.xyz, eps, dtype, direct_threshold=0.0, max_fft_bytes=16e6, deterministic=True) as p:
+        V = _np(p.synthesis(_t(wl.sky, dtype)))
+        I = _np(p.analysis(_t(wl.vis, dtype)))
+        assert p.info()["n_pairs_direct"] == 0
+        for t in (0, 3):
+            assert np.array_equal(V[t], _np(p.synthesis(_t(wl.sky[t], dtype)))[0])
+            assert np.array_equal(I[t], _np(p.analysis(_t(wl.vis[t], dtype)))[0])
+    es = oracle.rel_l2(V, oracle.synthesis(wl.uvw, wl.xyz, wl.sky))
+    ea = oracle.rel_l2(I, oracle.analysis(wl.uvw, wl.xyz, wl.vis))
+    print(f"[forced nufft 4 rows {dtype}] syn={es:.3e} ana={ea:.3e}", flush=True)
+    assert es <= eps and ea <= eps
+
+
+@pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
 def test_ntrans_hint_plans_match_oracle(dtype, eps):
     """Plans weighed for one and for four rows per call split the sub-problems
     differently between NUFFT grids and direct blocks; four-row calls through
