@@ -106,17 +106,23 @@ typedef struct {
                                  < 0  -> automatic (cost model);  0 -> never direct (forced NUFFT);
                                  +INFINITY -> always direct.  A positive finite value t makes a
                                  sub-problem direct when t * cost_direct <= cost_nufft. */
-    double workspace_bytes;   /* cap on the workspace shared by concurrently executed sub-problems;
-                                 0 -> 4 GiB (raised to the largest single sub-problem if needed). */
+    double workspace_bytes;   /* cap on the workspace shared by concurrently executed sub-problems
+                                 and the data rows of a NUFFT pass; 0 -> 4 GiB (raised to the
+                                 largest single sub-problem, per row, if needed). */
     const int32_t *vis_chunk; /* optional custom partition (host, [n_vis] chunk ids >= 0), replacing
                                  Algorithm 2 on the visibility domain (Sect. 4, allocate()). */
     const int32_t *sky_chunk; /* same for the sky domain ([n_pix]). */
     int32_t flags;            /* HVOX_REAL_SKY | HVOX_PLAN_HOST_ONLY | HVOX_TIMING | HVOX_PREORDERED |
                                  HVOX_DETERMINISTIC */
-    int32_t ntrans_hint;      /* data rows per call the NUFFT/direct choice is weighed for; 0 -> 1,
-                                 negative -> HVOX_ERR_ARG.  The direct sum shares its phase factors
-                                 among up to four rows while a NUFFT sub-problem repeats per row, so
-                                 batched calls favour direct blocks.  Results never depend on it. */
+    int32_t ntrans_hint;      /* data rows per call the plan is made for (Sect. 4, ntrans); 0 -> 1,
+                                 negative -> HVOX_ERR_ARG.  The NUFFT sub-problems run in passes of
+                                 min(4, ntrans_hint) rows that share the spreading and interpolation
+                                 weights, each row in its own copy of the batch workspace (the
+                                 workspace_bytes cap is split among them); the direct sum shares its
+                                 phase factors among up to four rows and, with the larger per-row
+                                 NUFFT cost, the choice between them is weighed for this many rows.
+                                 Results depend on it only through rounding (with
+                                 HVOX_DETERMINISTIC: not at all for an all-NUFFT plan). */
     hvox_alloc_fn dev_alloc;  /* optional device-memory hooks (see above); NULL -> hipMalloc / hipFree */
     hvox_free_fn  dev_free;
     void *alloc_ctx;          /* passed to both hooks */
@@ -158,6 +164,8 @@ typedef struct {
      * holding sources, x lines of grid 1 in tile rows holding sources, z planes in tile layers
      * holding sources; [0] occupied, [1] total */
     int64_t occ_tiles[2], occ_xlines[2], occ_zplanes[2];
+    int32_t nufft_rows;       /* data rows per NUFFT pass (min(4, ntrans_hint)) */
+    int32_t pad1;
 } hvox_plan_info_t;
 
 /* Per-kernel statistics of the calls since the last reset (HVOX_TIMING plans). */

@@ -27,18 +27,18 @@ hipError_t launch_bin(const PairDev *pairs, const int64_t *prefix, int npairs, i
                       hipStream_t st);
 template <typename T>
 hipError_t launch_prephase(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t, const int32_t *,
-                           const void *, void *, double, int, hipStream_t);
+                           const void *, int64_t, int, void *, void *, int64_t, double, int, hipStream_t);
 template <typename T>
-hipError_t launch_spread(const PairDev *, const SpreadTile *, int64_t, const int32_t *, const void *, void *, int, double,
-                         hipStream_t);
+hipError_t launch_spread(const PairDev *, const SpreadTile *, int64_t, const int32_t *, const void *, const void *,
+                         int64_t, int, void *, int64_t, int, double, hipStream_t);
 template <typename T>
 hipError_t launch_fft(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *, const void *,
-                      const uint32_t *, int, int, double, hipStream_t);
+                      const uint32_t *, int, int, double, int, int64_t, hipStream_t);
 template <typename T>
-hipError_t launch_transpose(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
+hipError_t launch_transpose(const PairDev *, const int64_t *, int, int64_t, void *, int, int64_t, hipStream_t);
 template <typename T>
 hipError_t launch_interp(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t, const double *,
-                         const void *, double *, int, double, double, int, hipStream_t);
+                         const void *, int64_t, double *, int64_t, int, int, double, double, int, hipStream_t);
 template <typename T>
 hipError_t launch_direct(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
                          const int32_t *, const void *, int64_t, double *, int64_t, int, double, int, int64_t,
@@ -254,6 +254,7 @@ struct Scratch {
     void *ws;
     void *stage;
     double *acc;
+    void *xval;   // staged values of rows 1 .. rows-1 of a NUFFT pass
 };
 
 // ---- executor -----------------------------------------------------------------
@@ -294,9 +295,9 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
     const bool overlap = may_time && !(p.flags & HVOX_TIMING) && !det && pl->side && !dp.batches.empty() &&
                          !dp.direct.empty();
     hipStream_t dst = overlap ? pl->side : st;
-    // rows in groups of up to kRowBatch: the NUFFT sub-problems run row by row
-    // into the group's accumulator rows, the direct sum covers all rows of the
-    // group in one launch (its phase factors are shared by the rows)
+    // rows in groups of up to kRowBatch: the NUFFT sub-problems run in passes of
+    // up to hp.rows rows into the group's accumulator rows, the direct sum covers
+    // all rows of the group in one launch (its phase factors are shared by the rows)
     for (int32_t t0 = 0; t0 < ntrans; t0 += kRowBatch) {
         const int nb = static_cast<int>(std::min<int32_t>(kRowBatch, ntrans - t0));
         if (n_tgt == 0) continue;
@@ -315,41 +316,46 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
             }
             HVOX_TRY(hipEventRecord(pl->join_ev, pl->side));
         }
-        for (int r = 0; r < nb; ++r) {
-            const C *in_t = static_cast<const C *>(in) + static_cast<int64_t>(t0 + r) * n_src;
-            double *acc_r = sc.acc + 2 * n_tgt * r;
+        // NUFFT sub-problems: passes of up to hp.rows data rows, each pass sharing the
+        // spreading and interpolation weights over its rows (row r in the r-th
+        // workspace copy and accumulator row)
+        for (int r0 = 0; r0 < nb; r0 += hp.rows) {
+            const int nr = std::min(hp.rows, nb - r0);
+            const C *in_t = static_cast<const C *>(in) + static_cast<int64_t>(t0 + r0) * n_src;
+            double *acc_r = sc.acc + 2 * n_tgt * r0;
             for (const Batch &b : dp.batches) {
                 const PairDev *pairs = dd.pairs + b.pair0;
                 const int np = static_cast<int>(b.npairs);
                 const int64_t *pprefix = dd.pre_pts + b.pre_pts;
                 HVOX_TRY(timed(pl, may_time, HVOX_K_PREPHASE, st, [&] {
-                    return launch_prephase<T>(pairs, pprefix, np, b.pts, sxyz, n_src, sperm, in_t, sc.stage, iota,
-                                              p.w, st);
+                    return launch_prephase<T>(pairs, pprefix, np, b.pts, sxyz, n_src, sperm, in_t, n_src, nr, sc.stage,
+                                              sc.xval, hp.max_pts, iota, p.w, st);
                 }));
                 HVOX_TRY(timed(pl, may_time, HVOX_K_SPREAD, st, [&] {
                     return launch_spread<T>(pairs, dd.spread_tiles + b.list_off, b.list_cnt, dd.records, sc.stage,
-                                            sc.ws, p.w, p.beta, st);
+                                            sc.xval, hp.max_pts, nr, sc.ws, hp.ws_row, p.w, p.beta, st);
                 }));
                 const int64_t n_add = dd.spread_add_cnt[&b - dp.batches.data()];
                 if (n_add > 0)
                     HVOX_TRY(timed(pl, may_time, HVOX_K_SPREAD, st, [&] {
                         return launch_spread<T>(pairs, dd.spread_tiles + b.list_off + b.list_cnt, n_add, dd.records,
-                                                sc.stage, sc.ws, p.w, p.beta, st);
+                                                sc.stage, sc.xval, hp.max_pts, nr, sc.ws, hp.ws_row, p.w, p.beta, st);
                     }));
                 for (int pass = 0; pass < 3; ++pass) {
                     HVOX_TRY(timed(pl, may_time, HVOX_K_FFT_X + pass, st, [&] {
                         return launch_fft<T>(pairs, dd.pre_tiles[pass] + b.pre_tiles[pass], np, b.tiles[pass], pass,
                                              sc.ws, pl->tw, pl->precor, dd.occ, b.lds_elems[pass],
-                                             b.max_pass_len[pass], iota, st);
+                                             b.max_pass_len[pass], iota, nr, hp.ws_row, st);
                     }));
                     if (pass == 0)
                         HVOX_TRY(timed(pl, may_time, HVOX_K_TRANSPOSE, st, [&] {
-                            return launch_transpose<T>(pairs, dd.pre_ttiles + b.pre_ttiles, np, b.ttiles, sc.ws, st);
+                            return launch_transpose<T>(pairs, dd.pre_ttiles + b.pre_ttiles, np, b.ttiles, sc.ws, nr,
+                                                       hp.ws_row, st);
                         }));
                 }
                 HVOX_TRY(timed(pl, may_time, HVOX_K_INTERP, st, [&] {
                     return launch_interp<T>(pairs, dd.pre_tgts + b.pre_tgts, np, b.iblocks, txyz, n_tgt, dd.deconv,
-                                            sc.ws, acc_r, p.w2, p.beta2, iota, det, st);
+                                            sc.ws, hp.ws_row, acc_r, 2 * n_tgt, nr, p.w2, p.beta2, iota, det, st);
                 }));
             }
         }
@@ -381,6 +387,16 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
     return HVOX_OK;
 }
 
+// the plan's own scratch: workspace, staged sources (footprint records, then
+// the further rows' values) and accumulator rows
+Scratch plan_scratch(const hvox_plan_s *pl)
+{
+    int64_t rec_b, val_b;
+    stage_layout(pl->hp, &rec_b, &val_b);
+    void *xval = pl->stage && val_b > 0 ? static_cast<char *>(pl->stage) + rec_b : nullptr;
+    return Scratch{pl->ws, pl->stage, pl->acc, xval};
+}
+
 int transform(hvox_plan_s *pl, bool synthesis, const void *in, void *out, int32_t ntrans, void *stream)
 {
     if (!pl) return fail(HVOX_ERR_STATE, "NULL plan");
@@ -393,7 +409,7 @@ int transform(hvox_plan_s *pl, bool synthesis, const void *in, void *out, int32_
     if (hipGetDevice(&cur) != hipSuccess) return fail(HVOX_ERR_HIP, "hipGetDevice failed");
     if (cur != pl->device) return fail(HVOX_ERR_STATE, "the plan's device is not the current device");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const Scratch sc{pl->ws, pl->stage, pl->acc};
+    const Scratch sc = plan_scratch(pl);
     if (pl->hp.prm.dtype == HVOX_F64) return run_direction<double>(pl, synthesis, in, out, ntrans, st, sc, true);
     return run_direction<float>(pl, synthesis, in, out, ntrans, st, sc, true);
 }
@@ -414,7 +430,7 @@ int run_dde(hvox_plan_s *pl, bool synthesis, const void *in, void *out, const vo
     using C = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
     C *X = static_cast<C *>(work);
     C *Y = X + static_cast<int64_t>(terms) * std::max(hp.n_vis, hp.n_pix);
-    const Scratch sc{pl->ws, pl->stage, pl->acc};
+    const Scratch sc = plan_scratch(pl);
     for (int32_t r = 0; r < ntrans; ++r) {
         const C *x_r = static_cast<const C *>(in) + static_cast<int64_t>(r) * n_in;
         C *y_r = static_cast<C *>(out) + static_cast<int64_t>(r) * n_out;
@@ -731,11 +747,10 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
         "accumulator");
     pl->acc = static_cast<double *>(tmp);
     chk(dev_alloc(pl, delta * static_cast<size_t>(hp.ws_elems), &pl->ws, false, st), "workspace");
-    int64_t max_pts = 0;
-    for (const DirPlan *dp : {&hp.syn, &hp.ana})
-        for (const Batch &b : dp->batches) max_pts = std::max(max_pts, b.pts);
-    const size_t staged = p.dtype == HVOX_F64 ? sizeof(StagedSrc<double>) : sizeof(StagedSrc<float>);
-    if (max_pts > 0) chk(dev_alloc(pl, staged * static_cast<size_t>(max_pts), &pl->stage, true, st), "source staging");
+    int64_t rec_b, val_b;
+    stage_layout(hp, &rec_b, &val_b);
+    if (hp.max_pts > 0)
+        chk(dev_alloc(pl, static_cast<size_t>(rec_b + val_b), &pl->stage, true, st), "source staging");
     if (rc) return bail(rc);
     // the direct sum's stream and the fork / join events; its grid is capped at
     // kDirectWgPerCu workgroups per CU so the NUFFT kernels find room beside it
@@ -788,11 +803,10 @@ constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 void static_scratch_layout(const HostPlan &hp, size_t *acc_b, size_t *stage_b, size_t *ws_b)
 {
     const bool f64 = hp.prm.dtype == HVOX_F64;
-    int64_t max_pts = 0;
-    for (const DirPlan *dp : {&hp.syn, &hp.ana})
-        for (const Batch &b : dp->batches) max_pts = std::max(max_pts, b.pts);
+    int64_t rec_b, val_b;
+    stage_layout(hp, &rec_b, &val_b);
     *acc_b = align256(16 * static_cast<size_t>(kRowBatch) * static_cast<size_t>(std::max(hp.n_vis, hp.n_pix)));
-    *stage_b = align256((f64 ? sizeof(StagedSrc<double>) : sizeof(StagedSrc<float>)) * static_cast<size_t>(max_pts));
+    *stage_b = align256(static_cast<size_t>(rec_b + val_b));
     *ws_b = align256((f64 ? 16 : 8) * static_cast<size_t>(hp.ws_elems));
 }
 
@@ -822,7 +836,10 @@ int transform_static(hvox_plan_s *pl, int32_t direction, const void *in, void *o
     const hipError_t e = static_scratch(cur, &base);
     if (e != hipSuccess) return fail(HVOX_ERR_HIP, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
     char *b = static_cast<char *>(base);
-    const Scratch sc{b + acc_b + stage_b, b + acc_b, reinterpret_cast<double *>(b)};
+    int64_t rec_b, val_b;
+    stage_layout(hp, &rec_b, &val_b);
+    const Scratch sc{b + acc_b + stage_b, b + acc_b, reinterpret_cast<double *>(b),
+                     val_b > 0 ? b + acc_b + rec_b : nullptr};
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (f64) return run_direction<double>(pl, synthesis, in, out, ntrans, st, sc, false);
     return run_direction<float>(pl, synthesis, in, out, ntrans, st, sc, false);
@@ -1116,6 +1133,7 @@ int hvox_plan_info(hvox_plan_t plan, hvox_plan_info_t *out)
         out->occ_xlines[q] = hp.syn.occ_xlines[q] + hp.ana.occ_xlines[q];
         out->occ_zplanes[q] = hp.syn.occ_zplanes[q] + hp.ana.occ_zplanes[q];
     }
+    out->nufft_rows = hp.rows;
     return HVOX_OK;
 }
 
@@ -1229,9 +1247,9 @@ extern "C" int hvox_test_fft(int32_t dtype, int32_t n, int32_t nin, int32_t nlin
     if (e == hipSuccess)
         e = dtype == HVOX_F64
                 ? launch_fft<double>(static_cast<PairDev *>(d_pd), static_cast<int64_t *>(d_pre), 1, tiles, 0, d_ws,
-                                     d_tw, d_one, nullptr, lds, n, sign, st)
+                                     d_tw, d_one, nullptr, lds, n, sign, 1, 0, st)
                 : launch_fft<float>(static_cast<PairDev *>(d_pd), static_cast<int64_t *>(d_pre), 1, tiles, 0, d_ws,
-                                    d_tw, d_one, nullptr, lds, n, sign, st);
+                                    d_tw, d_one, nullptr, lds, n, sign, 1, 0, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(out, static_cast<char *>(d_ws) + delta * gin, delta * gout, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -217,8 +217,14 @@ struct HostPlan {
     ChunkSet vis, sky;
     double h[3] = {0, 0, 0}, eta[3] = {0, 0, 0};
     DirPlan syn, ana;                    // syn: sky -> vis (iota = -1); ana: vis -> sky (iota = +1)
-    int64_t ws_elems = 0;                // workspace size (complex elements)
+    int64_t ws_elems = 0;                // workspace size (complex elements): rows copies of ws_row
     int64_t max_pair_ws = 0;
+    // data rows per NUFFT pass (the ntrans rows of Sect. 4, at most kRowBatch, from the
+    // caller's ntrans hint): the rows of a pass share the spreading and interpolation
+    // weights, and each takes its own copy of the batch workspace, ws_row elements apart
+    int rows = 1;
+    int64_t ws_row = 0;
+    int64_t max_pts = 0;                 // spread points of the largest batch
     // unique FFT-length tables: (n1, n2) pre-correction tables and n2 twiddles
     std::vector<double> precor_nu;       // nu = l / n2 of every pre-correction entry
     std::vector<int32_t> tw_len;         // lengths with a twiddle table
@@ -238,6 +244,16 @@ int make_host_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t 
                    const Params &prm, const int32_t *vis_chunk, const int32_t *sky_chunk,
                    HostPlan *hp, std::string *err);
 int32_t smooth_even(int64_t n);
+// bytes of the staged sources of one batch: the footprint records (with row 0's
+// values), rounded up to 256 bytes, then the values of rows 1 .. rows-1
+inline void stage_layout(const HostPlan &hp, int64_t *rec_bytes, int64_t *val_bytes)
+{
+    const bool f64 = hp.prm.dtype == HVOX_F64;
+    const int64_t rec = (f64 ? sizeof(StagedSrc<double>) : sizeof(StagedSrc<float>)) * hp.max_pts;
+    *rec_bytes = (rec + 255) / 256 * 256;
+    *val_bytes = (f64 ? 16 : 8) * static_cast<int64_t>(hp.rows - 1) * hp.max_pts;
+}
+
 // upper bound of the device bytes of a plan (resident tables + workspace), from the host plan
 int64_t device_bytes_bound(const HostPlan &hp);
 // complex elements a single sub-problem region may hold: kernels index within one

@@ -184,12 +184,15 @@ __global__ void k_bin_points(const PairDev *__restrict__ pairs, const int64_t *_
 // sub-problem of the batch, in the batch's order (sub-problem, then chunk
 // order), staged with its kernel footprint on grid 1 for the spreading pass
 // (computed once per source instead of once per tile it touches).  The phase
-// and the footprint are float64.
+// and the footprint are float64.  With several data rows in the pass (the
+// ntrans rows of Sect. 4), the footprint and phase factor are computed once
+// and the further rows' values go to xval, row-major with stride xstride.
 template <typename T>
 __global__ void k_prephase(const PairDev *__restrict__ pairs, const int64_t *__restrict__ pprefix, int npairs,
                            int64_t total, const double *__restrict__ xyz, int64_t nsrc,
-                           const int32_t *__restrict__ perm, const cplx<T> *__restrict__ in,
-                           StagedSrc<T> *__restrict__ stage, double iota, int w)
+                           const int32_t *__restrict__ perm, const cplx<T> *__restrict__ in, int64_t in_stride,
+                           int nr, StagedSrc<T> *__restrict__ stage, cplx<T> *__restrict__ xval, int64_t xstride,
+                           double iota, int w)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total) return;
@@ -202,7 +205,8 @@ __global__ void k_prephase(const PairDev *__restrict__ pairs, const int64_t *__r
     double ph = 0.0;
     for (int d = 0; d < 3; ++d) ph += P.sc[d] * xp[d];
     const double2 e = cis_cycles(ph, iota);
-    const cplx<T> c = in[perm ? perm[n] : n];   // no permutation: data already in chunk order
+    const int64_t u = perm ? perm[n] : n;   // no permutation: data already in chunk order
+    const cplx<T> c = in[u];
     StagedSrc<T> s;
     s.v[0] = T(c.x * e.x - c.y * e.y);
     s.v[1] = T(c.x * e.y + c.y * e.x);
@@ -211,6 +215,11 @@ __global__ void k_prephase(const PairDev *__restrict__ pairs, const int64_t *__r
         s.c0[d] = c0[d];
     }
     stage[g] = s;
+    // further data rows of the pass: the same phase factor, values only
+    for (int r = 1; r < nr; ++r) {
+        const cplx<T> cr = in[r * in_stride + u];
+        xval[(r - 1) * xstride + g] = mk<T>(T(cr.x * e.x - cr.y * e.y), T(cr.x * e.y + cr.y * e.x));
+    }
 }
 
 // eight consecutive LDS values (16-byte aligned) as wide reads
@@ -243,13 +252,17 @@ __device__ __forceinline__ void load8(const double *p, double v[8])
 // (a second launch) add their sums atomically on top (float atomics: the
 // rounding order of those cells varies from run to run).  The tile's sub-problem, corner and source list come from
 // one plan-time descriptor (the binning), each source's value and footprint
-// from the pre-phase pass.
-template <typename T>
+// from the pre-phase pass.  NR data rows share one evaluation of the kernel
+// weights (row r's grid is the r-th copy of the batch workspace, ws_stride
+// complex elements apart).
+template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pairs,
                                                 const SpreadTile *__restrict__ tiles,
                                                 const int32_t *__restrict__ records,
-                                                const StagedSrc<T> *__restrict__ staged, cplx<T> *__restrict__ ws,
-                                                int w, T beta, T two_over_w, float rwk)
+                                                const StagedSrc<T> *__restrict__ staged,
+                                                const cplx<T> *__restrict__ xval, int64_t xstride,
+                                                cplx<T> *__restrict__ ws, int64_t ws_stride, int w, T beta,
+                                                T two_over_w, float rwk)
 {
     static_assert(kTileZ == 8, "the z weights of a source are read as 8 values");
     // per staged source: kTileZ z values in the tile's frame, then w x and w y
@@ -258,7 +271,7 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
     static_assert(kKv % 4 == 0, "16-byte rows");
     __shared__ __align__(16) T kv[kSpreadBatch][kKv];
     __shared__ T frac[kSpreadBatch][3];
-    __shared__ cplx<T> val[kSpreadBatch];
+    __shared__ cplx<T> val[NR][kSpreadBatch];
     __shared__ int org[kSpreadBatch][3];
     const int tid = threadIdx.x;
     const SpreadTile tile = tiles[blockIdx.x];
@@ -268,20 +281,25 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
     static_assert(kTileX == 32 && kTileY == 8, "8 x 8 column patches per wavefront");
     const int x = (tid & 7) + 8 * (tid >> 6), y = (tid >> 3) & 7;
     const int wk = 2 * w + kTileZ;   // kernel values per staged source
-    T accr[kTileZ], acci[kTileZ];
+    T accr[NR][kTileZ], acci[NR][kTileZ];
 #pragma unroll
-    for (int z = 0; z < kTileZ; ++z) accr[z] = acci[z] = T(0);
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int z = 0; z < kTileZ; ++z) accr[r][z] = acci[r][z] = T(0);
 
     for (int base = 0; base < tile.cnt; base += kSpreadBatch) {
         const int cnt = min(kSpreadBatch, tile.cnt - base);
         __syncthreads();
         if (tid < cnt) {
-            const StagedSrc<T> sc = staged[records[tile.r0 + base + tid]];
+            const int32_t rec = records[tile.r0 + base + tid];
+            const StagedSrc<T> sc = staged[rec];
             for (int d = 0; d < 3; ++d) frac[tid][d] = sc.frac[d];
             org[tid][0] = sc.c0[0] - ox;
             org[tid][1] = sc.c0[1] - oy;
             org[tid][2] = sc.c0[2] - oz;
-            val[tid] = mk<T>(sc.v[0], sc.v[1]);
+            val[0][tid] = mk<T>(sc.v[0], sc.v[1]);
+#pragma unroll
+            for (int r = 1; r < NR; ++r) val[r][tid] = xval[(r - 1) * xstride + rec];
         }
         __syncthreads();
         // one branch-free evaluation per entry: z entries take their offset
@@ -299,35 +317,43 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
             const int qx = x - org[j][0], qy = y - org[j][1];
             if ((unsigned)qx >= (unsigned)w || (unsigned)qy >= (unsigned)w) continue;
             const T kxy = kv[j][kTileZ + qx] * kv[j][kTileZ + w + qy];
-            const T vr = val[j].x * kxy, vi = val[j].y * kxy;
             T kz[kTileZ];
             load8(kv[j], kz);
+            // the kernel weights of this source serve every data row
 #pragma unroll
-            for (int z = 0; z < kTileZ; ++z) {
-                accr[z] += vr * kz[z];
-                acci[z] += vi * kz[z];
+            for (int r = 0; r < NR; ++r) {
+                const T vr = val[r][j].x * kxy, vi = val[r][j].y * kxy;
+#pragma unroll
+                for (int z = 0; z < kTileZ; ++z) {
+                    accr[r][z] += vr * kz[z];
+                    acci[r][z] += vi * kz[z];
+                }
             }
         }
     }
     const PairDev &P = pairs[tile.pair];
     const int gx = ox + x, gy = oy + y;
     if (gx < P.n1[0] && gy < P.n1[1]) {
-        cplx<T> *grid = ws + P.bufG;
-        if (tile.flags & kSpreadAdd) {
 #pragma unroll
-            for (int z = 0; z < kTileZ; ++z) {
-                const int gz = oz + z;
-                if (gz < P.n1[2]) {
-                    T *c = reinterpret_cast<T *>(grid + ((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx);
-                    atomicAdd(c, accr[z]);
-                    atomicAdd(c + 1, acci[z]);
+        for (int r = 0; r < NR; ++r) {
+            cplx<T> *grid = ws + r * ws_stride + P.bufG;   // row r's copy of the batch workspace
+            if (tile.flags & kSpreadAdd) {
+#pragma unroll
+                for (int z = 0; z < kTileZ; ++z) {
+                    const int gz = oz + z;
+                    if (gz < P.n1[2]) {
+                        T *c = reinterpret_cast<T *>(grid + ((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx);
+                        atomicAdd(c, accr[r][z]);
+                        atomicAdd(c + 1, acci[r][z]);
+                    }
                 }
-            }
-        } else {
+            } else {
 #pragma unroll
-            for (int z = 0; z < kTileZ; ++z) {
-                const int gz = oz + z;
-                if (gz < P.n1[2]) grid[((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx] = mk<T>(accr[z], acci[z]);
+                for (int z = 0; z < kTileZ; ++z) {
+                    const int gz = oz + z;
+                    if (gz < P.n1[2])
+                        grid[((int64_t)gz * P.n1[1] + gy) * P.n1[0] + gx] = mk<T>(accr[r][z], acci[r][z]);
+                }
             }
         }
     }
@@ -447,16 +473,19 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int ls, int p, const cplx
 // plane is element j of every z-slab, so consecutive lines sit in adjacent
 // lanes).  The x pass also applies the separable pre-correction
 // 1/Phi_hat(l/n2) of all three axes (the (y, z) factor once per line) and
-// reads grid-1 tiles that hold no source as zeros.  Output
+// reads grid-1 tiles that hold no source as zeros.  The second grid
+// dimension runs over the data rows of the pass.  Output
 // q of the kept window is FFT index (wstart + q) mod n, written line-major:
 // out[line][q].
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pairs, const int64_t *__restrict__ prefix,
                                                  int npairs, int pass, cplx<T> *__restrict__ ws,
                                                  const cplx<T> *__restrict__ twtab, const T *__restrict__ precor,
-                                                 const uint32_t *__restrict__ occ, int tw_off, T s)
+                                                 const uint32_t *__restrict__ occ, int tw_off, T s,
+                                                 int64_t ws_stride)
 {
     static_assert(kTileX == 32, "a grid-1 tile spans 32 cells of an x line");
+    ws += (int64_t)blockIdx.y * ws_stride;   // data row blockIdx.y: its copy of the batch workspace
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *lds = reinterpret_cast<cplx<T> *>(smem_raw);
     cplx<T> *ltw = lds + tw_off;              // exp(s 2 pi i j/n), j < n, after the lines
@@ -589,9 +618,10 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
 // A[x'][y], through a padded LDS tile so reads and writes are both coalesced.
 template <typename T>
 __global__ __launch_bounds__(256) void k_transpose(const PairDev *__restrict__ pairs, const int64_t *__restrict__ prefix,
-                                                   int npairs, cplx<T> *__restrict__ ws)
+                                                   int npairs, cplx<T> *__restrict__ ws, int64_t ws_stride)
 {
     __shared__ cplx<T> tile[kTransposeTile][kTransposeTile + 1];
+    ws += (int64_t)blockIdx.y * ws_stride;   // data row blockIdx.y
     const int p = (int)find_segment(prefix, npairs, blockIdx.x);
     const PairDev &P = pairs[p];
     const int64_t local = (int64_t)blockIdx.x - prefix[p];
@@ -669,14 +699,17 @@ __device__ __forceinline__ void cis_rev(double t, double &c, double &s)
 // kInterpTargets targets of one sub-problem per workgroup);
 // the lanes cover the (y, z) pairs of its w^3 window (z fastest, as the
 // grid), loop over x, and reduce across the group.  Accumulation is float64
-// (cross-sub-problem sums stay in double precision).
+// (cross-sub-problem sums stay in double precision).  NR data rows share the
+// kernel weights, addresses and post-phase of each target (row r reads the
+// r-th copy of the batch workspace and adds into accumulator row r).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pairs, const int64_t *__restrict__ bprefix,
                                                 int npairs, int64_t block0, const double *__restrict__ xyz,
                                                 int64_t ntgt, const double *__restrict__ deconv,
-                                                const cplx<T> *__restrict__ ws, double *__restrict__ acc, int w,
-                                                T beta, double iota, int det)
+                                                const cplx<T> *__restrict__ ws, int64_t ws_stride,
+                                                double *__restrict__ acc, int64_t acc_stride, int w, T beta,
+                                                double iota, int det)
 {
     __shared__ T ker[kInterpTargets][3 * kWMax];
     const int sub = threadIdx.x & (kInterpLanes - 1), slot = threadIdx.x / kInterpLanes;
@@ -698,20 +731,22 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
             ker[slot][d * w + q] = es_kernel(T((double)(m0[d] + q) - tau) * two_over_w, beta);
     }
     __syncthreads();
-    T ar = T(0), ai = T(0);
+    T ar[NR], ai[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) ar[r] = ai[r] = T(0);
     if (active) {
         const int wx = P.wcount[0], wy = P.wcount[1], wz = P.wcount[2];
         const bool fx = wx == P.n2[0], fy = wy == P.n2[1], fz = wz == P.n2[2];   // whole (periodic) axis kept
         const int n2x = P.n2[0], n2y = P.n2[1], n2z = P.n2[2];
         const int sx = P.wstart[0], sy = P.wstart[1], sz = P.wstart[2];
-        const cplx<T> *grid = ws + P.bufA;          // [wx][wy][wz], z fastest
+        const cplx<T> *grid = ws + P.bufA;          // [wx][wy][wz], z fastest; row r at r * ws_stride
         const int xstride = wy * wz;
         // x cells eight at a time (the offsets and weights of a chunk shared by every
-        // (y, z) row of the target); cells beyond the kernel support or outside the
-        // kept window get weight 0 and the address of a cell the target reads anyway
-        // (its last column, clamped into the window), so the loads carry no branches
-        // and fetch no line the window does not need.  Each lane takes two (y, z)
-        // rows per step, sixteen loads in flight.
+        // (y, z) row of the target and every data row); cells beyond the kernel support
+        // or outside the kept window get weight 0 and the address of a cell the target
+        // reads anyway (its last column, clamped into the window), so the loads carry
+        // no branches and fetch no line the window does not need.  Each lane takes two
+        // (y, z) rows per step, sixteen loads in flight per data row.
         auto column = [&](int e, T &kyz) -> const cplx<T> * {
             const int dy = e / w, dz = e - dy * w;
             int qy = m0[1] + dy - sy, qz = m0[2] + dz - sz;
@@ -740,30 +775,36 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
                 const cplx<T> *col0 = column(e0, kyz0);
                 const cplx<T> *col1 = column(has1 ? e1 : e0, kyz1);   // no second row: a repeat, weight 0
                 if (!has1) kyz1 = T(0);
-                cplx<T> g0[8], g1[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    g0[u] = col0[xo[u]];
-                    g1[u] = col1[xo[u]];
-                }
-                T s0r = T(0), s0i = T(0), s1r = T(0), s1i = T(0);
+                for (int r = 0; r < NR; ++r) {
+                    const cplx<T> *c0 = col0 + r * ws_stride, *c1 = col1 + r * ws_stride;
+                    cplx<T> g0[8], g1[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    s0r += g0[u].x * kx[u];
-                    s0i += g0[u].y * kx[u];
-                    s1r += g1[u].x * kx[u];
-                    s1i += g1[u].y * kx[u];
+                    for (int u = 0; u < 8; ++u) {
+                        g0[u] = c0[xo[u]];
+                        g1[u] = c1[xo[u]];
+                    }
+                    T s0r = T(0), s0i = T(0), s1r = T(0), s1i = T(0);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        s0r += g0[u].x * kx[u];
+                        s0i += g0[u].y * kx[u];
+                        s1r += g1[u].x * kx[u];
+                        s1i += g1[u].y * kx[u];
+                    }
+                    ar[r] += s0r * kyz0 + s1r * kyz1;
+                    ai[r] += s0i * kyz0 + s1i * kyz1;
                 }
-                ar += s0r * kyz0 + s1r * kyz1;
-                ai += s0i * kyz0 + s1i * kyz1;
             }
         }
     }
     // reduce over the target's lane group (xor offsets below the group size stay inside it)
-    for (int off = kInterpLanes / 2; off > 0; off >>= 1) {
-        ar += __shfl_xor(ar, off, 64);
-        ai += __shfl_xor(ai, off, 64);
-    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        for (int off = kInterpLanes / 2; off > 0; off >>= 1) {
+            ar[r] += __shfl_xor(ar[r], off, 64);
+            ai[r] += __shfl_xor(ai[r], off, 64);
+        }
     if (active && sub == 0) {
         // post-phase exp(2 pi i iota s_k.x_c) in float64 in both precisions
         double ph = 0.0;
@@ -771,14 +812,18 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
         double er, ei;
         cis_rev(iota * ph, er, ei);
         const double dk = deconv[k];
-        const double vr = (double)ar * dk, vi = (double)ai * dk;
-        if (det) {
-            // deterministic plans: no other workgroup of this launch adds into target k
-            acc[2 * k] += vr * er - vi * ei;
-            acc[2 * k + 1] += vr * ei + vi * er;
-        } else {
-            atomicAdd(acc + 2 * k, vr * er - vi * ei);
-            atomicAdd(acc + 2 * k + 1, vr * ei + vi * er);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            double *a = acc + r * acc_stride;
+            const double vr = (double)ar[r] * dk, vi = (double)ai[r] * dk;
+            if (det) {
+                // deterministic plans: no other workgroup of this launch adds into target k
+                a[2 * k] += vr * er - vi * ei;
+                a[2 * k + 1] += vr * ei + vi * er;
+            } else {
+                atomicAdd(a + 2 * k, vr * er - vi * ei);
+                atomicAdd(a + 2 * k + 1, vr * ei + vi * er);
+            }
         }
     }
 }
@@ -1022,71 +1067,112 @@ hipError_t launch_bin(const PairDev *pairs, const int64_t *prefix, int npairs, i
 
 template <typename T>
 hipError_t launch_prephase(const PairDev *pairs, const int64_t *pprefix, int npairs, int64_t total, const double *xyz,
-                           int64_t nsrc, const int32_t *perm, const void *in, void *stage, double iota, int w,
-                           hipStream_t st)
+                           int64_t nsrc, const int32_t *perm, const void *in, int64_t in_stride, int rows, void *stage,
+                           void *xval, int64_t xstride, double iota, int w, hipStream_t st)
 {
     if (total <= 0) return hipSuccess;
+    if (rows < 1 || rows > kRowBatch) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_prephase<T>, dim3(blocks_for(total, 256, INT32_MAX)), dim3(256), 0, st, pairs, pprefix,
-                       npairs, total, xyz, nsrc, perm, static_cast<const cplx<T> *>(in),
-                       static_cast<StagedSrc<T> *>(stage), iota, w);
+                       npairs, total, xyz, nsrc, perm, static_cast<const cplx<T> *>(in), in_stride, rows,
+                       static_cast<StagedSrc<T> *>(stage), static_cast<cplx<T> *>(xval), xstride, iota, w);
     return hipGetLastError();
+}
+
+template <typename T, int NR>
+static void spread_rows(const PairDev *pairs, const SpreadTile *tiles, int64_t ntiles, const int32_t *records,
+                        const void *stage, const void *xval, int64_t xstride, void *ws, int64_t ws_stride, int w,
+                        double beta, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_spread<T, NR>), dim3(static_cast<unsigned>(ntiles)), dim3(256), 0, st, pairs, tiles, records,
+                       static_cast<const StagedSrc<T> *>(stage), static_cast<const cplx<T> *>(xval), xstride,
+                       static_cast<cplx<T> *>(ws), ws_stride, w, T(beta), T(2.0 / w),
+                       1.0f / static_cast<float>(2 * w + kTileZ));
 }
 
 template <typename T>
 hipError_t launch_spread(const PairDev *pairs, const SpreadTile *tiles, int64_t ntiles, const int32_t *records,
-                         const void *stage, void *ws, int w, double beta, hipStream_t st)
+                         const void *stage, const void *xval, int64_t xstride, int rows, void *ws, int64_t ws_stride,
+                         int w, double beta, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spread<T>, dim3(static_cast<unsigned>(ntiles)), dim3(256), 0, st, pairs, tiles, records,
-                       static_cast<const StagedSrc<T> *>(stage), static_cast<cplx<T> *>(ws), w, T(beta), T(2.0 / w),
-                       1.0f / static_cast<float>(2 * w + kTileZ));
+    switch (rows) {
+    case 1: spread_rows<T, 1>(pairs, tiles, ntiles, records, stage, xval, xstride, ws, ws_stride, w, beta, st); break;
+    case 2: spread_rows<T, 2>(pairs, tiles, ntiles, records, stage, xval, xstride, ws, ws_stride, w, beta, st); break;
+    case 3: spread_rows<T, 3>(pairs, tiles, ntiles, records, stage, xval, xstride, ws, ws_stride, w, beta, st); break;
+    case 4: spread_rows<T, 4>(pairs, tiles, ntiles, records, stage, xval, xstride, ws, ws_stride, w, beta, st); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_fft(const PairDev *pairs, const int64_t *prefix, int npairs, int64_t tiles, int pass, void *ws,
                       const void *tw, const void *precor, const uint32_t *occ, int lds_elems, int max_len, double sign,
-                      hipStream_t st)
+                      int rows, int64_t ws_stride, hipStream_t st)
 {
     if (tiles <= 0) return hipSuccess;
+    if (rows < 1 || rows > kRowBatch) return hipErrorInvalidValue;
     // dynamic LDS: the lines of one workgroup, then the twiddle table of the longest line
     size_t lds = static_cast<size_t>(lds_elems + max_len) * sizeof(cplx<T>);
     const T *pc = static_cast<const T *>(precor);
+    const dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>(rows));
     // workgroup size from the longest line of the batch (lines up to kFftSmallLen: 256 threads)
     if (fft_threads(max_len) == kFftThreadsSmall)
-        hipLaunchKernelGGL((k_fft_pass<T, kFftThreadsSmall>), dim3(static_cast<unsigned>(tiles)), dim3(kFftThreadsSmall),
-                           lds, st, pairs, prefix, npairs, pass, static_cast<cplx<T> *>(ws),
-                           static_cast<const cplx<T> *>(tw), pc, occ, lds_elems, T(sign));
+        hipLaunchKernelGGL((k_fft_pass<T, kFftThreadsSmall>), grid, dim3(kFftThreadsSmall), lds, st, pairs, prefix,
+                           npairs, pass, static_cast<cplx<T> *>(ws), static_cast<const cplx<T> *>(tw), pc, occ,
+                           lds_elems, T(sign), ws_stride);
     else
-        hipLaunchKernelGGL((k_fft_pass<T, kFftThreads>), dim3(static_cast<unsigned>(tiles)), dim3(kFftThreads), lds, st,
-                           pairs, prefix, npairs, pass, static_cast<cplx<T> *>(ws), static_cast<const cplx<T> *>(tw),
-                           pc, occ, lds_elems, T(sign));
+        hipLaunchKernelGGL((k_fft_pass<T, kFftThreads>), grid, dim3(kFftThreads), lds, st, pairs, prefix, npairs, pass,
+                           static_cast<cplx<T> *>(ws), static_cast<const cplx<T> *>(tw), pc, occ, lds_elems, T(sign),
+                           ws_stride);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_transpose(const PairDev *pairs, const int64_t *prefix, int npairs, int64_t tiles, void *ws,
-                            hipStream_t st)
+                            int rows, int64_t ws_stride, hipStream_t st)
 {
     if (tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_transpose<T>, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, st, pairs, prefix, npairs,
-                       static_cast<cplx<T> *>(ws));
+    if (rows < 1 || rows > kRowBatch) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_transpose<T>, dim3(static_cast<unsigned>(tiles), static_cast<unsigned>(rows)), dim3(256), 0,
+                       st, pairs, prefix, npairs, static_cast<cplx<T> *>(ws), ws_stride);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_interp(const PairDev *pairs, const int64_t *bprefix, int npairs, int64_t blocks, const double *xyz,
-                         int64_t ntgt, const double *deconv, const void *ws, double *acc, int w, double beta,
-                         double iota, int det, hipStream_t st)
+template <typename T, int NR>
+static hipError_t interp_rows(const PairDev *pairs, const int64_t *bprefix, int npairs, int64_t blocks,
+                              const double *xyz, int64_t ntgt, const double *deconv, const void *ws,
+                              int64_t ws_stride, double *acc, int64_t acc_stride, int w, double beta, double iota,
+                              int det, hipStream_t st)
 {
     for (int64_t b0 = 0; b0 < blocks; b0 += kMaxLaunchBlocks) {
         const int64_t nb = std::min<int64_t>(kMaxLaunchBlocks, blocks - b0);
-        hipLaunchKernelGGL(k_interp<T>, dim3(static_cast<unsigned>(nb)), dim3(256), 0, st, pairs, bprefix, npairs, b0,
-                           xyz, ntgt, deconv, static_cast<const cplx<T> *>(ws), acc, w, T(beta), iota, det);
+        hipLaunchKernelGGL((k_interp<T, NR>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, st, pairs, bprefix,
+                           npairs, b0, xyz, ntgt, deconv, static_cast<const cplx<T> *>(ws), ws_stride, acc,
+                           acc_stride, w, T(beta), iota, det);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_interp(const PairDev *pairs, const int64_t *bprefix, int npairs, int64_t blocks, const double *xyz,
+                         int64_t ntgt, const double *deconv, const void *ws, int64_t ws_stride, double *acc,
+                         int64_t acc_stride, int rows, int w, double beta, double iota, int det, hipStream_t st)
+{
+    if (blocks <= 0) return hipSuccess;
+    switch (rows) {
+    case 1: return interp_rows<T, 1>(pairs, bprefix, npairs, blocks, xyz, ntgt, deconv, ws, ws_stride, acc,
+                                     acc_stride, w, beta, iota, det, st);
+    case 2: return interp_rows<T, 2>(pairs, bprefix, npairs, blocks, xyz, ntgt, deconv, ws, ws_stride, acc,
+                                     acc_stride, w, beta, iota, det, st);
+    case 3: return interp_rows<T, 3>(pairs, bprefix, npairs, blocks, xyz, ntgt, deconv, ws, ws_stride, acc,
+                                     acc_stride, w, beta, iota, det, st);
+    case 4: return interp_rows<T, 4>(pairs, bprefix, npairs, blocks, xyz, ntgt, deconv, ws, ws_stride, acc,
+                                     acc_stride, w, beta, iota, det, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T, int NT>
@@ -1147,24 +1233,29 @@ hipError_t launch_finalize(const double *acc, int64_t n, const int32_t *perm, vo
 }
 
 template hipError_t launch_prephase<float>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
-                                           const int32_t *, const void *, void *, double, int, hipStream_t);
+                                           const int32_t *, const void *, int64_t, int, void *, void *, int64_t, double,
+                                           int, hipStream_t);
 template hipError_t launch_prephase<double>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
-                                           const int32_t *, const void *, void *, double, int, hipStream_t);
-template hipError_t launch_spread<float>(const PairDev *, const SpreadTile *, int64_t, const int32_t *,
-                                         const void *, void *, int, double, hipStream_t);
-template hipError_t launch_spread<double>(const PairDev *, const SpreadTile *, int64_t, const int32_t *,
-                                         const void *, void *, int, double, hipStream_t);
+                                            const int32_t *, const void *, int64_t, int, void *, void *, int64_t,
+                                            double, int, hipStream_t);
+template hipError_t launch_spread<float>(const PairDev *, const SpreadTile *, int64_t, const int32_t *, const void *,
+                                         const void *, int64_t, int, void *, int64_t, int, double, hipStream_t);
+template hipError_t launch_spread<double>(const PairDev *, const SpreadTile *, int64_t, const int32_t *, const void *,
+                                          const void *, int64_t, int, void *, int64_t, int, double, hipStream_t);
 template hipError_t launch_fft<float>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,
-                                      const void *, const uint32_t *, int, int, double, hipStream_t);
+                                      const void *, const uint32_t *, int, int, double, int, int64_t, hipStream_t);
 template hipError_t launch_fft<double>(const PairDev *, const int64_t *, int, int64_t, int, void *, const void *,
-                                       const void *, const uint32_t *, int, int, double, hipStream_t);
-template hipError_t launch_transpose<float>(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
-template hipError_t launch_transpose<double>(const PairDev *, const int64_t *, int, int64_t, void *, hipStream_t);
+                                       const void *, const uint32_t *, int, int, double, int, int64_t, hipStream_t);
+template hipError_t launch_transpose<float>(const PairDev *, const int64_t *, int, int64_t, void *, int, int64_t,
+                                            hipStream_t);
+template hipError_t launch_transpose<double>(const PairDev *, const int64_t *, int, int64_t, void *, int, int64_t,
+                                             hipStream_t);
 template hipError_t launch_interp<float>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
-                                         const double *, const void *, double *, int, double, double, int, hipStream_t);
+                                         const double *, const void *, int64_t, double *, int64_t, int, int, double,
+                                         double, int, hipStream_t);
 template hipError_t launch_interp<double>(const PairDev *, const int64_t *, int, int64_t, const double *, int64_t,
-                                          const double *, const void *, double *, int, double, double, int,
-                                          hipStream_t);
+                                          const double *, const void *, int64_t, double *, int64_t, int, int, double,
+                                          double, int, hipStream_t);
 template hipError_t launch_direct<float>(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
                                          const int32_t *, const void *, int64_t, double *, int64_t, int, double, int,
                                          int64_t, hipStream_t);

@@ -820,7 +820,7 @@ int64_t device_bytes_bound(const HostPlan &hp)
         temp = std::max(temp, 12 * dp->tiles_total);                            // binning counts + cursors
         b += 4 * ((dp->tiles_total + 31) / 32 + kOccWords);                     // tile occupancy bits
     }
-    b += staged * max_pts;
+    b += staged * max_pts + delta * static_cast<int64_t>(hp.rows - 1) * max_pts + 256;   // staged sources
     b += delta * hp.ws_elems;
     return b + temp;
 }
@@ -961,9 +961,10 @@ int make_host_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t 
     s_floor(hp->sky, syn_in.s_floor);
     s_floor(hp->vis, ana_in.s_floor);
 
-    // workspace: the caller's cap (each direction raises its batching cap to its
-    // largest NUFFT sub-problem)
-    hp->ws_elems = static_cast<int64_t>(p.ws_cap / delta);
+    // workspace: the caller's cap, shared by the rows of a pass (each direction
+    // raises its batching cap to its largest NUFFT sub-problem)
+    hp->rows = std::max(1, std::min(kRowBatch, p.ntrans_hint));
+    hp->ws_elems = static_cast<int64_t>(p.ws_cap / delta / hp->rows);
 
     std::map<std::pair<int32_t, int32_t>, int64_t> precor_map;
     std::map<int32_t, int64_t> tw_map;
@@ -973,11 +974,17 @@ int make_host_plan(const double *uvw, int64_t n_vis, const double *xyz, int64_t 
     plan_direction(*hp, ana_in, &hp->ana, &precor_map, &hp->precor_nu, &tw_map, &max_ws_ana);
 
     hp->max_pair_ws = std::max(max_ws_syn, max_ws_ana);
-    // actual workspace: the largest batch
-    int64_t used = 0;
+    // actual workspace: the largest batch, once per row of a pass (row copies
+    // 64 elements aligned)
+    int64_t used = 0, max_pts = 0;
     for (const DirPlan *dp : {&hp->syn, &hp->ana})
-        for (const Batch &b : dp->batches) used = std::max(used, b.ws_end);
-    hp->ws_elems = used;
+        for (const Batch &b : dp->batches) {
+            used = std::max(used, b.ws_end);
+            max_pts = std::max(max_pts, b.pts);
+        }
+    hp->ws_row = hp->rows > 1 ? (used + 63) / 64 * 64 : used;
+    hp->ws_elems = hp->ws_row * hp->rows;
+    hp->max_pts = max_pts;
 
     hp->tw_len.clear();
     hp->tw_off.clear();

@@ -226,6 +226,30 @@ def test_ntrans_hint_shifts_the_choice_towards_direct():
         hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True, ntrans_hint=-1)
 
 
+def test_row_passes_split_the_workspace():
+    """NUFFT sub-problems run in passes of min(4, ntrans_hint) data rows, each
+    row in its own copy of the batch workspace: the copies share the caller's
+    workspace cap (batches shrink to fit), and the device-bytes bound covers the
+    copies and the further rows' staged values."""
+    wl = W.ska_like(n_pix=60000, n_ant=60, n_times=12)
+    cap = 64e6
+    infos = {}
+    for hint in (1, 2, 4, 9):
+        with hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True, direct_threshold=0.0, ntrans_hint=hint,
+                     max_fft_bytes=4e6, workspace_bytes=cap) as p:
+            infos[hint] = p.info()
+    for hint, i in infos.items():
+        assert i["nufft_rows"] == min(4, hint)
+        assert i["n_pairs_direct"] == 0 and i["n_pairs_nufft"] == infos[1]["n_pairs_nufft"]
+        per_row = i["workspace_bytes"] / i["nufft_rows"]
+        assert per_row <= max(cap / i["nufft_rows"], i["max_pair_workspace_bytes"]) + 64 * 8
+        assert i["workspace_bytes"] <= cap + 4 * 64 * 8
+        assert i["device_bytes"] > i["workspace_bytes"]
+    # smaller per-row caps: at least as many batches
+    assert infos[4]["n_batches"] >= infos[2]["n_batches"] >= infos[1]["n_batches"]
+    assert infos[4]["n_batches"] > infos[1]["n_batches"]
+
+
 def test_automatic_choice_is_never_worse_than_either_pure_mode():
     """Per pair the planner takes the cheaper of the two evaluations (pairs
     whose direct cost is under the least a NUFFT sub-problem can cost skip the
