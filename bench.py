@@ -308,13 +308,13 @@ def main():
     ap.add_argument("--modes", default="",
                     help="comma-separated subset of the runs reported beside the headline (forced_nufft, all_direct, "
                          "batched_ntrans4, forced_nufft_ntrans4, dense_10km, dense_10km_all_direct, dense_30km, "
-                         "sparse_100km, sparse_100km_forced_nufft); default all")
+                         "sparse_100km, sparse_100km_forced_nufft, compact_f64, lofar_f32); default all")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the runs reported beside the headline (forced NUFFT, all direct, four rows, the dense "
                          "mesh, serving)")
     ap.add_argument("--lofar", action="store_true",
-                    help="also time the LOFAR-like wide-field workload (5.0M vis x 4M pix, 60-degree cap) in float32 "
-                         "at eps = 1e-4 and float64 at eps = 1e-9 (about two minutes more)")
+                    help="time the LOFAR-like wide-field workload (5.0M vis x 4M pix, 60-degree cap) in float64 at "
+                         "eps = 1e-9 too (about two minutes more; its float32 step at eps = 1e-4 is a default mode)")
     ap.add_argument("--workload", choices=("ska-like", "dense-10km"), default="ska-like",
                     help="the workload of the reported step: the SKA-like 995k vis x 1M pix cap (default, the "
                          "metric's workload) or the dense 30-degree DCOS mesh of the 10 km rung (238k vis x 10.24M "
@@ -396,7 +396,7 @@ def main():
     wanted = set(filter(None, args.modes.split(","))) or {"forced_nufft", "all_direct", "batched_ntrans4",
                                                            "dense_10km", "dense_10km_all_direct", "dense_30km",
                                                            "sparse_100km", "sparse_100km_forced_nufft",
-                                                           "forced_nufft_ntrans4"}
+                                                           "forced_nufft_ntrans4", "compact_f64", "lofar_f32"}
     if not args.no_modes:
         # the two other execution modes of the float32 transform: every sub-problem as a
         # NUFFT (the path the spread / FFT / interp rooflines describe), every one direct
@@ -436,6 +436,19 @@ def main():
         if "sparse_100km_forced_nufft" in wanted:
             modes["sparse_100km_forced_nufft"] = run_mode("f32", 1e-4, 0.0, 5, 1, work=sparse)
         del sparse
+    if not (args.no_modes or dense_head) and "compact_f64" in wanted:
+        # the small float64 case (2,000 vis x 3,072 pix, eps = 1e-6), timed beside the
+        # oracle's full sums in the CPU leg
+        compact = W.compact_disk()
+        log(f"workload {compact.name}")
+        modes["compact_f64"] = run_mode("f64", 1e-6, args.direct_threshold, 20, 2, work=compact)
+        del compact
+    if not (args.no_modes or dense_head) and "lofar_f32" in wanted and not args.lofar:
+        # the LOFAR-like wide field (5.0M vis x 4M pix, 60-degree cap), one float32 step
+        lofar = W.lofar_like()
+        log(f"workload {lofar.name}")
+        modes["lofar_f32"] = run_mode("f32", 1e-4, args.direct_threshold, 1, 0, work=lofar)
+        del lofar
     if args.lofar:
         lofar = W.lofar_like()
         log(f"workload {lofar.name}")
@@ -539,6 +552,17 @@ def main():
         for m, r in modes.items():
             if r["wl"] is wl:
                 out["modes"][m]["rel_l2_vs_oracle"] = errs(r["V"][rv], r["I"][rp], Vs[0], Is[0], len(rv))
+            elif m == "compact_f64":
+                # every output row, and the oracle's own time for the whole step
+                ow = r["wl"]
+                t0 = time.perf_counter()
+                Vo = oracle.synthesis(ow.uvw, ow.xyz, ow.sky)[0]
+                Io = oracle.analysis(ow.uvw, ow.xyz, ow.vis)[0]
+                t_or = time.perf_counter() - t0
+                out["modes"][m]["rel_l2_vs_oracle"] = errs(r["V"], r["I"], Vo, Io, ow.n_vis + ow.n_pix)
+                out["modes"][m]["oracle"] = {"ms_per_step": t_or * 1e3, "value": r["n_units"] / t_or,
+                                             "cores": oracle.max_threads(),
+                                             "gpu_over_oracle": t_or / r["sec"]}
             else:   # another workload: its own sampled rows
                 ow = r["wl"]
                 rv2 = W.sample_rows(ow.n_vis, 256, seed=51)

@@ -166,6 +166,7 @@ typedef struct {
     int64_t occ_tiles[2], occ_xlines[2], occ_zplanes[2];
     int32_t nufft_rows;       /* data rows per NUFFT pass (min(4, ntrans_hint)) */
     int32_t pad1;
+    double  est_direct_seconds;   /* the direct sub-problems' part of est_seconds */
 } hvox_plan_info_t;
 
 /* Per-kernel statistics of the calls since the last reset (HVOX_TIMING plans). */

@@ -258,6 +258,11 @@ struct Scratch {
 };
 
 // ---- executor -----------------------------------------------------------------
+// largest estimated direct-sum share of a direction's time at which the overlapped
+// direct sum runs on a capped persistent grid (measured on one MI355X: SKA-like cap,
+// direct share 0.75, 609 ms capped vs 624 ms uncapped; LOFAR-like wide field, share
+// 0.93, 14.39 s capped vs 12.71 s uncapped)
+constexpr double kCappedDirectShare = 0.85;
 template <typename T>
 int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, int32_t ntrans, hipStream_t st,
                   const Scratch &sc, bool may_time, bool allow_real = true)
@@ -295,6 +300,11 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
     const bool overlap = may_time && !(p.flags & HVOX_TIMING) && !det && pl->side && !dp.batches.empty() &&
                          !dp.direct.empty();
     hipStream_t dst = overlap ? pl->side : st;
+    // beside a sizeable NUFFT share the direct sum takes a persistent grid capped per
+    // CU, leaving room for the NUFFT kernels; when it is nearly the whole estimated
+    // time (wide fields) it takes one workgroup per item, every CU full of its waves
+    const double direct_share = dp.est_seconds > 0.0 ? dp.est_direct_seconds / dp.est_seconds : 1.0;
+    const int64_t direct_cap = direct_share <= kCappedDirectShare ? pl->direct_grid_cap : 0;
     // rows in groups of up to kRowBatch: the NUFFT sub-problems run in passes of
     // up to hp.rows rows into the group's accumulator rows, the direct sum covers
     // all rows of the group in one launch (its phase factors are shared by the rows)
@@ -311,7 +321,7 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
                 HVOX_TRY(timed(pl, may_time, HVOX_K_DIRECT, dst, [&] {
                     return launch_direct<T>(dd.direct + i0, i1 - i0, sxyz, n_src, txyz, n_tgt, sperm,
                                             static_cast<const C *>(in) + static_cast<int64_t>(t0) * n_src, n_src,
-                                            sc.acc, 2 * n_tgt, nb, iota, det, pl->direct_grid_cap, dst);
+                                            sc.acc, 2 * n_tgt, nb, iota, det, direct_cap, dst);
                 }));
             }
             HVOX_TRY(hipEventRecord(pl->join_ev, pl->side));
@@ -1134,6 +1144,7 @@ int hvox_plan_info(hvox_plan_t plan, hvox_plan_info_t *out)
         out->occ_zplanes[q] = hp.syn.occ_zplanes[q] + hp.ana.occ_zplanes[q];
     }
     out->nufft_rows = hp.rows;
+    out->est_direct_seconds = hp.syn.est_direct_seconds + hp.ana.est_direct_seconds;
     return HVOX_OK;
 }
 

@@ -184,6 +184,7 @@ struct DirPlan {                         // one direction (synthesis or analysis
     double grid_cells = 0.0, direct_terms = 0.0;
     int64_t occ_tiles[2] = {0, 0}, occ_xlines[2] = {0, 0}, occ_zplanes[2] = {0, 0};   // filled by the binning
     double est_seconds = 0.0;
+    double est_direct_seconds = 0.0;     // the direct sub-problems' share of est_seconds
     double alg_bytes[HVOX_K_COUNT] = {0};
     double alg_flops[HVOX_K_COUNT] = {0};
 };

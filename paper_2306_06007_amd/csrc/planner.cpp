@@ -524,7 +524,7 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
     struct Cand { int32_t i, j; PairGeom g; };
     std::vector<Cand> nufft;
     dp->direct.clear();
-    dp->grid_cells = dp->direct_terms = dp->est_seconds = 0.0;
+    dp->grid_cells = dp->direct_terms = dp->est_seconds = dp->est_direct_seconds = 0.0;
     for (auto &v : dp->alg_bytes) v = 0.0;
     for (auto &v : dp->alg_flops) v = 0.0;
 
@@ -553,6 +553,7 @@ void plan_direction(const HostPlan &hp, const DirInputs &in, DirPlan *dp,
                 (p.direct_threshold != 0.0 && thr * t_dir <= nufft_seconds_floor(ns, nt, p) * p.ntrans_hint);
             auto take_direct = [&]() {
                 dp->est_seconds += t_dir;
+                dp->est_direct_seconds += t_dir;
                 dp->direct_terms += static_cast<double>(ns) * nt;
                 if (ns == 0) return;
                 if (!ranges.empty() && ranges.back().second == src.off[i]) ranges.back().second = src.off[i + 1];

@@ -75,7 +75,8 @@ class HvoxPlanInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("flags", ctypes.c_int32), ("on_device", ctypes.c_int32),
                 ("n_direct_layers", ctypes.c_int64), ("noalloc_scratch_bytes", ctypes.c_int64),
                 ("occ_tiles", ctypes.c_int64 * 2), ("occ_xlines", ctypes.c_int64 * 2),
-                ("occ_zplanes", ctypes.c_int64 * 2), ("nufft_rows", ctypes.c_int32), ("pad1", ctypes.c_int32)]
+                ("occ_zplanes", ctypes.c_int64 * 2), ("nufft_rows", ctypes.c_int32), ("pad1", ctypes.c_int32),
+                ("est_direct_seconds", ctypes.c_double)]
 
 
 class HvoxStats(ctypes.Structure):

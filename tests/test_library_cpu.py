@@ -250,6 +250,21 @@ def test_row_passes_split_the_workspace():
     assert infos[4]["n_batches"] > infos[1]["n_batches"]
 
 
+def test_direct_share_of_the_estimate():
+    """plan_info splits the cost-model estimate: the direct part is all of it in an
+    all-direct plan, none of it in a forced-NUFFT plan, and between for the
+    automatic choice (the executor caps the overlapped direct grid by this share)."""
+    wl = W.ska_like()                            # full size: its automatic plan mixes both
+    infos = {}
+    for name, thr in (("auto", -1.0), ("nufft", 0.0), ("direct", float("inf"))):
+        with hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True, direct_threshold=thr) as p:
+            infos[name] = p.info()
+    assert infos["direct"]["est_direct_seconds"] == pytest.approx(infos["direct"]["est_seconds"], rel=1e-12)
+    assert infos["nufft"]["est_direct_seconds"] == 0.0
+    a = infos["auto"]
+    assert 0.0 < a["est_direct_seconds"] < a["est_seconds"]
+
+
 def test_automatic_choice_is_never_worse_than_either_pure_mode():
     """Per pair the planner takes the cheaper of the two evaluations (pairs
     whose direct cost is under the least a NUFFT sub-problem can cost skip the
