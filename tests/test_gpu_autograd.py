@@ -133,3 +133,48 @@ def test_gradient_full_size_sampled():
     bound = eps * np.linalg.norm(gc) / np.linalg.norm(g_ref)     # eps on A^H r, over ||Re A^H r||
     print(f"[full-size gradient] sampled rel-l2 vs oracle adjoint {err:.3e} (bound {bound:.3e})", flush=True)
     assert err <= bound
+
+
+@pytest.mark.slow
+def test_gradient_at_zero_full_size_sampled():
+    """The same full-size problem at x0 = 0, where the model predicts nothing:
+    the gradient of 0.5 ||A x - y||^2 is -Re(A^H y); the float32 gradient on
+    4,096 sampled pixels is held to eps ||A^H y|| / ||Re A^H y|| of the oracle's
+    adjoint of y, and two central differences along seeded unit directions to
+    eps ||g||."""
+    import torch
+    wl = W.ska_like()
+    rng = np.random.default_rng(5)
+    x_true = rng.random(wl.n_pix)
+    with hv.Plan(wl.uvw, wl.xyz, 1e-9, "f64") as p64:
+        Ax = p64.synthesis(torch.as_tensor(x_true[None]).to("cuda", torch.complex128))[0].cpu().numpy()
+    y = Ax + W.noise_for_snr(float(np.vdot(Ax, Ax).real), wl.n_vis, 20.0, rng)
+    eps = 1e-4
+    with hv.Plan(wl.uvw, wl.xyz, eps, "f32") as p:
+        y128 = torch.as_tensor(y).to("cuda", torch.complex128)
+        x = torch.zeros(wl.n_pix, dtype=torch.float32, device="cuda", requires_grad=True)
+        V = HvoxSynthesis.apply(x, p)
+        assert float(V.detach().abs().max()) == 0.0
+        (0.5 * (V - y128.to(torch.complex64)).abs().pow(2).sum()).backward()
+        g = x.grad.double().cpu().numpy()
+
+        def loss(xv):
+            Vx = p.synthesis(torch.as_tensor(xv[None]).to("cuda", torch.complex64))[0]
+            return 0.5 * float((Vx.to(torch.complex128) - y128).abs().pow(2).sum())
+
+        gn = float(np.linalg.norm(g))
+        tau = 100.0   # central differences of a quadratic are exact at any step
+        x0 = np.zeros(wl.n_pix)
+        for k in range(2):
+            d = rng.normal(size=wl.n_pix)
+            d /= np.linalg.norm(d)
+            fd = (loss(x0 + tau * d) - loss(x0 - tau * d)) / (2 * tau)
+            print(f"[gradient at zero] direction {k}: fd={fd:.6e} g.d={g @ d:.6e} |g|={gn:.3e}", flush=True)
+            assert abs(fd - g @ d) <= eps * gn, (k, fd, g @ d, gn)
+    rp = W.sample_rows(wl.n_pix, 4096, seed=63)
+    gc = -oracle.analysis(wl.uvw, wl.xyz, y[None], rows=rp)[0]
+    g_ref = gc.real
+    err = oracle.rel_l2(g[rp], g_ref)
+    bound = eps * np.linalg.norm(gc) / np.linalg.norm(g_ref)     # eps on A^H y, over ||Re A^H y||
+    print(f"[gradient at zero] sampled rel-l2 vs oracle adjoint {err:.3e} (bound {bound:.3e})", flush=True)
+    assert err <= bound
