@@ -81,6 +81,44 @@ def test_preordered_data_skips_the_permutations():
         assert np.array_equal(Vq, V[:, vp]) and np.array_equal(Iq, I[:, sp])
 
 
+def test_preordered_row_passes():
+    """Pre-ordered data through NUFFT passes of three rows (a plan made for four rows
+    per call): bit-identical to the permuted path of the same plan options."""
+    wl = W.ska_like(n_pix=15000, n_ant=40, n_times=8, ntrans=3)
+    kw = dict(max_fft_bytes=8e6, deterministic=True, direct_threshold=0.0, ntrans_hint=4)
+    for dtype in ("f32", "f64"):
+        eps = 1e-4 if dtype == "f32" else 1e-9
+        with hv.Plan(wl.uvw, wl.xyz, eps, dtype, **kw) as p:
+            assert p.info()["nufft_rows"] == 4
+            V = _np(p.synthesis(_t(wl.sky, dtype)))
+            I = _np(p.analysis(_t(wl.vis, dtype)))
+            vp, sp = p.permutation()
+        with hv.Plan(wl.uvw, wl.xyz, eps, dtype, preordered=True, **kw) as q:
+            Vq = _np(q.synthesis(_t(wl.sky[:, sp], dtype)))
+            Iq = _np(q.analysis(_t(wl.vis[:, vp], dtype)))
+        assert np.array_equal(Vq, V[:, vp]) and np.array_equal(Iq, I[:, sp])
+
+
+@pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
+def test_deterministic_row_passes_on_crowded_tiles(dtype, eps):
+    """Crowded spreading tiles (walked whole in deterministic plans) through
+    passes of two rows: each row bit-identical to the plan made for one row per
+    call, and within eps of the oracle."""
+    uvw, xyz, sky, vis = _crowded()
+    rng = np.random.default_rng(19)
+    sky2 = np.concatenate([sky, W.complex_normal(1, xyz.shape[0], rng)])
+    vis2 = np.concatenate([vis, W.complex_normal(1, uvw.shape[0], rng)])
+    outs = {}
+    for hint in (1, 2):
+        with hv.Plan(uvw, xyz, eps, dtype, deterministic=True, direct_threshold=0.0, max_fft_bytes=4e6,
+                     ntrans_hint=hint) as p:
+            assert p.info()["nufft_rows"] == hint
+            outs[hint] = (_np(p.synthesis(_t(sky2, dtype))), _np(p.analysis(_t(vis2, dtype))))
+    assert np.array_equal(outs[1][0], outs[2][0]) and np.array_equal(outs[1][1], outs[2][1])
+    assert oracle.rel_l2(outs[2][0], oracle.synthesis(uvw, xyz, sky2)) <= eps
+    assert oracle.rel_l2(outs[2][1], oracle.analysis(uvw, xyz, vis2)) <= eps
+
+
 class CountingAllocator:
     """dev_alloc / dev_free hooks over PyTorch's caching allocator that count
     the blocks and can be told to fail after a number of bytes."""

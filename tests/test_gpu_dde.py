@@ -31,21 +31,23 @@ def _np(t):
 
 
 @pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
-@pytest.mark.parametrize("thr", [-1.0, 0.0])
-def test_dde_small_against_dense_oracle(dtype, eps, thr):
+@pytest.mark.parametrize("thr,hint", [(-1.0, 1), (0.0, 1), (0.0, 4)])
+def test_dde_small_against_dense_oracle(dtype, eps, thr, hint):
+    """Three gain terms: with a plan made for four rows per call they go through
+    one NUFFT pass of three rows."""
     rng = np.random.default_rng(21)
     wl = W.compact_disk(n_vis=900, n_pix=1100, ntrans=2)
     terms = 3
     a = rng.normal(size=(terms, wl.n_vis)) + 1j * rng.normal(size=(terms, wl.n_vis))
     b = rng.normal(size=(terms, wl.n_pix)) + 1j * rng.normal(size=(terms, wl.n_pix))
-    with hv.Plan(wl.uvw, wl.xyz, eps, dtype, direct_threshold=thr, max_fft_bytes=4e6) as p:
+    with hv.Plan(wl.uvw, wl.xyz, eps, dtype, direct_threshold=thr, max_fft_bytes=4e6, ntrans_hint=hint) as p:
         V = _np(p.synthesis_dde(_t(wl.sky, dtype), _t(a, dtype), _t(b, dtype)))
         I = _np(p.analysis_dde(_t(wl.vis, dtype), _t(a, dtype), _t(b, dtype)))
     Vref = dde.synthesis_dense(wl.uvw, wl.xyz, wl.sky, a, b)
     Iref = dde.analysis_dense(wl.uvw, wl.xyz, wl.vis, a, b)
     es, ea = oracle.rel_l2(V, Vref), oracle.rel_l2(I, Iref)
     ms, ma = oracle.max_rel_err(V, Vref), oracle.max_rel_err(I, Iref)
-    print(f"[dde {dtype} thr={thr}] syn {es:.2e} (max {ms:.2e}) ana {ea:.2e} (max {ma:.2e})", flush=True)
+    print(f"[dde {dtype} thr={thr} hint={hint}] syn {es:.2e} (max {ms:.2e}) ana {ea:.2e} (max {ma:.2e})", flush=True)
     assert es <= eps and ea <= eps
     assert ms <= 5 * eps and ma <= 5 * eps
 

@@ -40,7 +40,8 @@ def _t(a, cd):
 
 
 @pytest.mark.parametrize("dtype,eps", [("f32", 1e-4), ("f64", 1e-9)])
-def test_noalloc_matches_the_allocating_entry_point(dtype, eps):
+@pytest.mark.parametrize("hint", [1, 2])
+def test_noalloc_matches_the_allocating_entry_point(dtype, eps, hint):
     import torch
     cd = torch.complex64 if dtype == "f32" else torch.complex128
     big = W.compact_disk(ntrans=2)                       # 2,000 vis x 3,072 pix, two rows
@@ -48,8 +49,8 @@ def test_noalloc_matches_the_allocating_entry_point(dtype, eps):
     nufft = dict(max_fft_bytes=16e6, workspace_bytes=40e6, direct_threshold=0.0)   # ~38 MB of scratch
     direct = dict(max_fft_bytes=16e6, workspace_bytes=40e6, direct_threshold=1.0)
     for wl, kw in ((big, nufft), (small, nufft), (big, direct), (small, direct)):
-        with hv.Plan(wl.uvw, wl.xyz, eps, dtype, deterministic=True, **kw) as p:
-            assert p.info()["noalloc_scratch_bytes"] <= (64 << 20)
+        with hv.Plan(wl.uvw, wl.xyz, eps, dtype, deterministic=True, ntrans_hint=hint, **kw) as p:
+            assert p.info()["noalloc_scratch_bytes"] <= (64 << 20)   # two-row plans: passes of two rows
             sky, vis = _t(wl.sky, cd), _t(wl.vis, cd)
             rc_s, Vs = _noalloc(p, 0, sky)
             rc_a, Is = _noalloc(p, 1, vis)
@@ -62,7 +63,7 @@ def test_noalloc_matches_the_allocating_entry_point(dtype, eps):
         Vn, In = Vs.cpu().numpy(), Is.cpu().numpy()
         assert oracle.rel_l2(Vn, oracle.synthesis(wl.uvw, wl.xyz, wl.sky)) <= eps
         assert oracle.rel_l2(In, oracle.analysis(wl.uvw, wl.xyz, wl.vis)) <= eps
-        print(f"[noalloc {dtype}] {wl.name}: nufft={info['n_pairs_nufft']} direct={info['n_pairs_direct']} "
+        print(f"[noalloc {dtype} hint={hint}] {wl.name}: nufft={info['n_pairs_nufft']} direct={info['n_pairs_direct']} "
               f"workspace={info['workspace_bytes']}", flush=True)
 
 
