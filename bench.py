@@ -501,7 +501,7 @@ def main():
     }
     if "forced_nufft" in modes:
         # the rooflines of the NUFFT kernels on the forced-NUFFT step (every sub-problem a
-        # type-3 NUFFT): spreading (grid fills included) and interpolation are the graded ones
+        # type-3 NUFFT): spreading and interpolation are the graded ones
         fr = modes["forced_nufft"]
         out["nufft_rooflines"] = {}
         for k in ("spread", "interp", "fft_x", "fft_y", "fft_z", "transpose", "prephase"):

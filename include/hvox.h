@@ -171,7 +171,7 @@ typedef struct {
 
 /* Per-kernel statistics of the calls since the last reset (HVOX_TIMING plans). */
 #define HVOX_K_ZERO     0   /* accumulator clears */
-#define HVOX_K_SPREAD   1   /* spreading, with the grid-1 fills of mostly empty batches */
+#define HVOX_K_SPREAD   1   /* spreading over the occupied grid-1 tiles */
 #define HVOX_K_FFT_X    2
 #define HVOX_K_FFT_Y    3
 #define HVOX_K_FFT_Z    4
@@ -223,7 +223,8 @@ int hvox_plan_upload(hvox_plan_t plan, void *stream);
  * sky: device [ntrans][n_pix] complex, vis: device [ntrans][n_vis] complex.
  * Rows are processed in groups of up to four: the direct sub-problems of a
  * group share their phase factors across its rows (one kernel launch), the
- * NUFFT sub-problems run row by row into the group's accumulator rows. */
+ * NUFFT sub-problems run in passes of up to min(4, ntrans_hint) rows that
+ * share the spreading and interpolation weights (Sect. 4, ntrans). */
 int hvox_synthesis(hvox_plan_t plan, const void *sky, void *vis, int32_t ntrans, void *stream);
 
 /* vis -> sky:  sky[t][n] = sum_k vis[t][k] exp(+2 pi i <p_k, r_n>)   (Eq. 3, the adjoint)

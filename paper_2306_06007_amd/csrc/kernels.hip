@@ -5,8 +5,13 @@
 // Data layout in HBM
 //  * coordinates: float64 structure-of-arrays [3][n] in chunk order;
 //  * user data:   complex (float2 / double2) in user order, gathered through
-//                 the chunk-order permutation (Sect. 4, chunk-order views);
-//  * grids:       per batch of sub-problems one workspace with three regions:
+//                 the chunk-order permutation (Sect. 4, chunk-order views), or
+//                 already in chunk order (pre-ordered plans);
+//  * occupancy:   one bit per grid-1 tile (32 x 8 x 8 cells), set when the
+//                 tile holds sources; spreading writes only those tiles and
+//                 the x pass reads the others as zeros;
+//  * grids:       per batch of sub-problems and per data row of a pass one
+//                 workspace copy with three regions:
 //                 G holds every pair's grid 1 as [n1z][n1y][n1x]; the x pass
 //                 writes its kept window line-major to B ([n1z][n1y][wx]), a
 //                 tiled transpose moves it to A ([n1z][wx][n1y]), the y pass
@@ -90,7 +95,7 @@ static_assert(int64_t(kFftMaxLen / kTileX) * (kFftMaxLen / kTileY) * (kFftMaxLen
               "grid-1 tiles of a sub-problem must fit 31 bits");
 
 // ---------------------------------------------------------------------------
-// fills
+// accumulator clear
 // ---------------------------------------------------------------------------
 __global__ void k_zero(double *__restrict__ p, int64_t n)
 {
@@ -123,7 +128,7 @@ __global__ void k_deconv(const double *__restrict__ xyz, int64_t n, const int32_
 }
 
 // ---------------------------------------------------------------------------
-// spreading (type-3 step 1, "spreading ... followed by tapering" of Sect. 3):
+// spreading (type-3 step 1, Sect. 3):
 //   b_l = sum_n c'_n prod_d ES((l_d - t_nd) 2/w),  c'_n = c_n exp(2 pi i iota s_c.x'_n),
 // with t_n = (x_n - x_c) * kscale (grid-1 units) and l in [-n1/2, n1/2)^3.
 // ---------------------------------------------------------------------------
@@ -838,11 +843,11 @@ __global__ __launch_bounds__(256) void k_interp(const PairDev *__restrict__ pair
 //   s_k.x_n = s_k.x_S + s_T.(x_n - x_S) + (s_k - s_T).(x_n - x_S):
 // the first two terms are evaluated once per (target, tile) and
 // (source, tile); only the small third term is evaluated per (target,
-// source) pair.  Every phase is reduced to [-1/2, 1/2) turn in float64 and
-// its sine / cosine taken in the plan's precision (cis_rev).  The sign iota
-// is folded into the staged values (c exp(-i t) = conj(conj(c) exp(+i t))),
-// so the inner loop always
-// accumulates c exp(+2 pi i t).  Phases are float64 (full rate on CDNA).
+// source) pair.  Every phase is reduced to a fraction of a turn in float64
+// and its sine / cosine taken in the plan's precision for the per-pair term
+// (cis_rev), in float64 for the per-tile reference terms.  The sign iota
+// multiplies the target offsets and the reference phases, so the inner loop
+// always accumulates c exp(+2 pi i t).  Phases are float64 (full rate on CDNA).
 // ---------------------------------------------------------------------------
 
 template <typename T, int NT>

@@ -28,7 +28,7 @@ constexpr double kPi = 3.14159265358979323846;
 
 // Cost-model rates used to choose NUFFT or direct summation for each
 // sub-problem, from MI355X kernel timings: the grid passes (FFT passes,
-// transpose, fills) sustain ~3e12 algorithmic bytes/s of the byte model
+// transpose) sustain ~3e12 algorithmic bytes/s of the byte model
 // below and the spreading / interpolation kernels ~4e11 kernel-cell updates/s
 // in float32 and ~8e11 in float64 (its 14-wide footprints fill more lanes of
 // a wavefront, and float64 FMAs issue at the float32 rate); the direct
