@@ -312,6 +312,31 @@ def test_degenerate_inputs(case):
         assert es <= eps and ea <= eps
 
 
+@pytest.mark.parametrize("case", ["one_vis", "one_pix", "duplicates", "planar_sky"])
+def test_degenerate_inputs_in_row_passes(case):
+    """The degenerate inputs again, three data rows through one NUFFT pass of a
+    plan made for four rows per call (every sub-problem a NUFFT)."""
+    rng = np.random.default_rng(12)
+    uvw = W.uvw_disk(400, 500.0, 20.0, rng)
+    xyz = W.fibonacci_cap(500, 5.0)
+    if case == "one_vis":
+        uvw = uvw[:1]
+    elif case == "one_pix":
+        xyz = xyz[:1]
+    elif case == "duplicates":
+        uvw[100:200] = uvw[0]
+        xyz[50:90] = xyz[3]
+    elif case == "planar_sky":
+        xyz = xyz.copy(); xyz[:, 2] = 1.0
+    sky = W.complex_normal(3, xyz.shape[0], rng)
+    vis = W.complex_normal(3, uvw.shape[0], rng)
+    for dtype, eps in (("f64", 1e-9), ("f32", 1e-4)):
+        es, ea, info = both_directions(uvw, xyz, sky, vis, eps, dtype, direct_threshold=0.0, ntrans_hint=4)
+        assert info["nufft_rows"] == 4
+        _report(case + " rows", es, ea, info)
+        assert es <= eps and ea <= eps
+
+
 def test_empty_domains():
     import torch
     xyz = W.fibonacci_cap(50, 5.0)
