@@ -42,7 +42,7 @@ hipError_t launch_interp(const PairDev *, const int64_t *, int, int64_t, const d
 template <typename T>
 hipError_t launch_direct(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
                          const int32_t *, const void *, int64_t, double *, int64_t, int, double, int, int64_t,
-                         hipStream_t);
+                         const void *, hipStream_t);
 template <typename T>
 hipError_t launch_finalize(const double *, int64_t, const int32_t *, void *, int, hipStream_t);
 template <typename T>
@@ -98,6 +98,7 @@ struct hvox_plan_s {
     int32_t *vis_perm = nullptr, *sky_perm = nullptr;
     void *precor = nullptr;                             // pre-correction tables in the plan's precision
     void *tw = nullptr;
+    void *cis_tab = nullptr;                            // float64 plans: exp(2 pi i k / kCisTab), the direct sum's table
     hvox::DevDir syn, ana;
     void *ws = nullptr;
     void *stage = nullptr;                              // staged sources of one batch (value and footprint)
@@ -321,7 +322,7 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
                 HVOX_TRY(timed(pl, may_time, HVOX_K_DIRECT, dst, [&] {
                     return launch_direct<T>(dd.direct + i0, i1 - i0, sxyz, n_src, txyz, n_tgt, sperm,
                                             static_cast<const C *>(in) + static_cast<int64_t>(t0) * n_src, n_src,
-                                            sc.acc, 2 * n_tgt, nb, iota, det, direct_cap, dst);
+                                            sc.acc, 2 * n_tgt, nb, iota, det, direct_cap, pl->cis_tab, dst);
                 }));
             }
             HVOX_TRY(hipEventRecord(pl->join_ev, pl->side));
@@ -378,7 +379,7 @@ int run_direction(hvox_plan_s *pl, bool synthesis, const void *in, void *out, in
             HVOX_TRY(timed(pl, may_time, HVOX_K_DIRECT, st, [&] {
                 return launch_direct<T>(dd.direct + i0, i1 - i0, sxyz, n_src, txyz, n_tgt, sperm,
                                         static_cast<const C *>(in) + static_cast<int64_t>(t0) * n_src, n_src, sc.acc,
-                                        2 * n_tgt, nb, iota, det, 0, st);
+                                        2 * n_tgt, nb, iota, det, 0, pl->cis_tab, st);
             }));
         }
         for (int r = 0; r < nb; ++r) {
@@ -695,7 +696,7 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
     }
     // twiddles exp(-2 pi i j / n); the host tables stay alive until the
     // stream synchronisation that ends the plan upload
-    std::vector<double2> tw64;
+    std::vector<double2> tw64, cis64;
     std::vector<float2> tw32;
     if (p.dtype == HVOX_F64) {
         tw64.resize(hp.tw_total);
@@ -707,6 +708,15 @@ int build_device(hvox_plan_s *pl, hipStream_t st, std::string *err)
         double2 *d = nullptr;
         chk(upload(pl, tw64, &d, st), "twiddles");
         pl->tw = d;
+        // the direct sum's phase table: exp(2 pi i k / kCisTab)
+        cis64.resize(kCisTab);
+        for (int k = 0; k < kCisTab; ++k) {
+            const double a = 2.0 * M_PI * k / kCisTab;
+            cis64[k] = make_double2(std::cos(a), std::sin(a));
+        }
+        double2 *dc = nullptr;
+        chk(upload(pl, cis64, &dc, st), "phase table");
+        pl->cis_tab = dc;
     } else {
         tw32.resize(hp.tw_total);
         for (size_t t = 0; t < hp.tw_len.size(); ++t)
@@ -1045,7 +1055,7 @@ int hvox_plan_upload(hvox_plan_t plan, void *stream)
         release(plan);
         plan->vis_xyz = plan->sky_xyz = nullptr;
         plan->vis_perm = plan->sky_perm = nullptr;
-        plan->precor = plan->tw = plan->ws = plan->stage = nullptr;
+        plan->precor = plan->tw = plan->ws = plan->stage = plan->cis_tab = nullptr;
         plan->acc = nullptr;
         plan->syn = DevDir{};
         plan->ana = DevDir{};

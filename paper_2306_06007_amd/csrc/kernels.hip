@@ -697,6 +697,28 @@ __device__ __forceinline__ void cis_rev(double t, double &c, double &s)
     c = (k == 1 || k == 2) ? -c1 : c1;
 }
 
+// exp(2 pi i t) in float64 from a table of exp(2 pi i k / kCisTab) (float64,
+// filled on the host) and the Taylor terms of the remainder: with u =
+// kCisTab frac(t), k = rint(u) and f = u - k in [-1/2, 1/2], t = (k + f) /
+// kCisTab modulo one turn and exp(2 pi i t) = tab[k mod kCisTab] exp(i theta),
+// theta = 2 pi f / kCisTab, |theta| <= pi / kCisTab; sin theta ~ theta -
+// theta^3 / 6 and cos theta ~ 1 - theta^2 / 2 + theta^4 / 24 leave a
+// truncation below theta^5 / 120 = 2.3e-15 (kCisTab = 1024).  The fraction,
+// the scaling by a power of two and the split u = k + f are exact.
+__device__ __forceinline__ void cis_tab(double t, const double2 *tab, double &c, double &s)
+{
+    static_assert((kCisTab & (kCisTab - 1)) == 0, "power-of-two table");
+    const double u = __builtin_amdgcn_fract(t) * kCisTab;   // [0, kCisTab)
+    const double kf = rint(u);                               // [0, kCisTab]; kCisTab wraps to entry 0
+    const double th = (u - kf) * (6.283185307179586476925287 / kCisTab);
+    const double th2 = th * th;
+    const double sn = fma(th * th2, -1.0 / 6.0, th);
+    const double cs = fma(th2, fma(th2, 1.0 / 24.0, -0.5), 1.0);
+    const double2 e = tab[static_cast<int>(kf) & (kCisTab - 1)];
+    c = fma(e.x, cs, -e.y * sn);
+    s = fma(e.y, cs, e.x * sn);
+}
+
 // ---------------------------------------------------------------------------
 // interpolation + deconvolution + post-phase (type-3 steps 3-4):
 //   f_k += exp(2 pi i iota s_k.x_c) / prod Psi_hat(.) * sum_m G_m prod_d ES((m_d - tau_kd) 2/w)
@@ -856,7 +878,7 @@ __device__ __forceinline__ void direct_item(const DirectItem it, const double *_
                                             const int32_t *__restrict__ perm, const cplx<T> *__restrict__ in,
                                             int64_t in_stride, double *__restrict__ acc, int64_t acc_stride,
                                             double iota, int det, double *lx, double *ly, double *lz,
-                                            cplx<T> (*lc)[kDirectSrcTile])
+                                            cplx<T> (*lc)[kDirectSrcTile], const double2 *ltab)
 {
     const int tid = threadIdx.x;
     // two targets per thread: each staged source is read from LDS once for both
@@ -910,8 +932,13 @@ __device__ __forceinline__ void direct_item(const DirectItem it, const double *_
             const double t0 = fma(sp0[0], xj, fma(sp0[1], yj, sp0[2] * zj));
             const double t1 = fma(sp1[0], xj, fma(sp1[1], yj, sp1[2] * zj));
             T c0, s0v, c1, s1v;
-            cis_rev(t0, c0, s0v);
-            cis_rev(t1, c1, s1v);
+            if constexpr (sizeof(T) == 8) {   // float64 plan: the LDS phase table
+                cis_tab(t0, ltab, c0, s0v);
+                cis_tab(t1, ltab, c1, s1v);
+            } else {                          // float32 plan: the hardware sine / cosine
+                cis_rev(t0, c0, s0v);
+                cis_rev(t1, c1, s1v);
+            }
             // one phase factor per (target, source), applied to every row
 #pragma unroll
             for (int r = 0; r < NT; ++r) {
@@ -971,15 +998,20 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(const DirectItem *__r
                                                            const int32_t *__restrict__ perm,
                                                            const cplx<T> *__restrict__ in, int64_t in_stride,
                                                            double *__restrict__ acc, int64_t acc_stride, double iota,
-                                                           int det)
+                                                           int det, const double2 *__restrict__ ctab)
 {
     static_assert(kDirectSrcTile == kDirectThreads && kDirectTile == 2 * kDirectThreads, "direct tiling");
     __shared__ double lx[kDirectSrcTile], ly[kDirectSrcTile], lz[kDirectSrcTile];
     __shared__ cplx<T> lc[NT][kDirectSrcTile];
+    __shared__ double2 ltab[sizeof(T) == 8 ? kCisTab : 1];   // float64 plans: the phase table
+    if constexpr (sizeof(T) == 8) {
+        for (int i = threadIdx.x; i < kCisTab; i += kDirectThreads) ltab[i] = ctab[i];
+        // the first item's staging barrier orders these writes before any read
+    }
     for (int64_t w = blockIdx.x; w < nitems; w += gridDim.x) {
         if (w != blockIdx.x) __syncthreads();   // the previous item's last tile is read before restaging
         direct_item<T, NT>(items[w], sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc, acc_stride, iota, det, lx, ly,
-                           lz, lc);
+                           lz, lc, ltab);
     }
 }
 
@@ -1184,14 +1216,15 @@ template <typename T, int NT>
 static hipError_t launch_direct_rows(const DirectItem *items, int64_t nitems, const double *sxyz, int64_t nsrc,
                                      const double *txyz, int64_t ntgt, const int32_t *perm, const void *in,
                                      int64_t in_stride, double *acc, int64_t acc_stride, double iota, int det,
-                                     int64_t grid_cap, hipStream_t st)
+                                     int64_t grid_cap, const void *ctab, hipStream_t st)
 {
+    const double2 *tab = static_cast<const double2 *>(ctab);
     if (grid_cap > 0) {
         // persistent: at most grid_cap workgroups looping over the items
         const int64_t nb = std::min<int64_t>(std::min<int64_t>(grid_cap, nitems), kMaxLaunchBlocks);
         hipLaunchKernelGGL((k_direct<T, NT>), dim3(static_cast<unsigned>(nb)), dim3(kDirectThreads), 0, st, items,
                            nitems, sxyz, nsrc, txyz, ntgt, perm, static_cast<const cplx<T> *>(in), in_stride, acc,
-                           acc_stride, iota, det);
+                           acc_stride, iota, det, tab);
         return hipGetLastError();
     }
     // one workgroup per item, in launches of at most kMaxLaunchBlocks workgroups
@@ -1200,7 +1233,7 @@ static hipError_t launch_direct_rows(const DirectItem *items, int64_t nitems, co
         const int64_t nb = std::min<int64_t>(kMaxLaunchBlocks, nitems - i0);
         hipLaunchKernelGGL((k_direct<T, NT>), dim3(static_cast<unsigned>(nb)), dim3(kDirectThreads), 0, st,
                            items + i0, nb, sxyz, nsrc, txyz, ntgt, perm, static_cast<const cplx<T> *>(in), in_stride,
-                           acc, acc_stride, iota, det);
+                           acc, acc_stride, iota, det, tab);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1211,18 +1244,19 @@ template <typename T>
 hipError_t launch_direct(const DirectItem *items, int64_t nitems, const double *sxyz, int64_t nsrc,
                          const double *txyz, int64_t ntgt, const int32_t *perm, const void *in, int64_t in_stride,
                          double *acc, int64_t acc_stride, int rows, double iota, int det, int64_t grid_cap,
-                         hipStream_t st)
+                         const void *ctab, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
+    if (sizeof(T) == 8 && ctab == nullptr) return hipErrorInvalidValue;   // float64: the phase table
     switch (rows) {
     case 1: return launch_direct_rows<T, 1>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
-                                            acc_stride, iota, det, grid_cap, st);
+                                            acc_stride, iota, det, grid_cap, ctab, st);
     case 2: return launch_direct_rows<T, 2>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
-                                            acc_stride, iota, det, grid_cap, st);
+                                            acc_stride, iota, det, grid_cap, ctab, st);
     case 3: return launch_direct_rows<T, 3>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
-                                            acc_stride, iota, det, grid_cap, st);
+                                            acc_stride, iota, det, grid_cap, ctab, st);
     case 4: return launch_direct_rows<T, 4>(items, nitems, sxyz, nsrc, txyz, ntgt, perm, in, in_stride, acc,
-                                            acc_stride, iota, det, grid_cap, st);
+                                            acc_stride, iota, det, grid_cap, ctab, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1263,10 +1297,10 @@ template hipError_t launch_interp<double>(const PairDev *, const int64_t *, int,
                                           double, int, hipStream_t);
 template hipError_t launch_direct<float>(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
                                          const int32_t *, const void *, int64_t, double *, int64_t, int, double, int,
-                                         int64_t, hipStream_t);
+                                         int64_t, const void *, hipStream_t);
 template hipError_t launch_direct<double>(const DirectItem *, int64_t, const double *, int64_t, const double *, int64_t,
                                           const int32_t *, const void *, int64_t, double *, int64_t, int, double, int,
-                                          int64_t, hipStream_t);
+                                          int64_t, const void *, hipStream_t);
 template <typename T>
 hipError_t launch_dde_scale(const void *w, const void *x, void *out, int64_t n, int terms, int conj_w, hipStream_t st)
 {

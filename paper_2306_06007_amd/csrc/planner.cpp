@@ -32,7 +32,7 @@ constexpr double kPi = 3.14159265358979323846;
 // below and the spreading / interpolation kernels ~4e11 kernel-cell updates/s
 // in float32 and ~8e11 in float64 (its 14-wide footprints fill more lanes of
 // a wavefront, and float64 FMAs issue at the float32 rate); the direct
-// kernel 3.0e12 (float32) and 9.2e11 (float64) terms/s.  A sweep of the
+// kernel 3.0e12 (float32) and 1.35e12 (float64) terms/s.  A sweep of the
 // decision threshold on the SKA-like and dense DCOS workloads puts the
 // fastest split at these rates (threshold 1).
 struct Rates {
@@ -44,7 +44,7 @@ struct Rates {
 
 Rates rates_for(int dtype)
 {
-    if (dtype == HVOX_F64) return {3.0e12, 8.0e11, 9.2e11, 4e-6};
+    if (dtype == HVOX_F64) return {3.0e12, 8.0e11, 1.35e12, 4e-6};
     return {3.0e12, 4.0e11, 3.0e12, 4e-6};
 }
 
@@ -502,11 +502,11 @@ double pair_direct_seconds(int64_t ns, int64_t nt, int dtype)
 // Cost of `rows` data rows relative to one: the direct kernel evaluates each
 // phase factor once for up to kRowBatch rows, so every further row of a group
 // adds only its multiply-adds (about 2 of the 11 issue cycles of a float32
-// term and 4 of the 42 of a float64 term, from the direct kernel's inner-loop
+// term and 4 of the 24 of a float64 term, from the direct kernel's inner-loop
 // instruction counts); a NUFFT sub-problem repeats every stage per row.
 double direct_rows_factor(int rows, int dtype)
 {
-    const double extra = dtype == HVOX_F64 ? 4.0 / 42.25 : 2.0 / 11.125;
+    const double extra = dtype == HVOX_F64 ? 4.0 / 24.25 : 2.0 / 11.125;
     double f = 0.0;
     for (int r = rows; r > 0; r -= kRowBatch) f += 1.0 + extra * (std::min(r, kRowBatch) - 1);
     return f;
@@ -799,6 +799,7 @@ int64_t device_bytes_bound(const HostPlan &hp)
     int64_t b = 24 * (nv + np) + 4 * (nv + np) + 8 * (nv + np) + 4 * (nv + np);   // coords, perms, deconv, chunk ids
     b += 16 * static_cast<int64_t>(kRowBatch) * std::max(nv, np);                // accumulator
     b += prec * static_cast<int64_t>(hp.precor_nu.size()) + delta * hp.tw_total;
+    if (p.dtype == HVOX_F64) b += 16 * kCisTab;                                 // direct-sum phase table
     const int nq = 2 * std::max(p.w, p.w2) + 60;
     b += 16 * nq + 48 * (static_cast<int64_t>(hp.vis.nc) + hp.sky.nc);          // quadrature, centres, scales
     const int per_dim[3] = {(p.w - 1 + kTileX - 1) / kTileX + 1, (p.w - 1 + kTileY - 1) / kTileY + 1,
