@@ -485,7 +485,9 @@ def main():
                    "n_vis": wl.n_vis, "n_pix": wl.n_pix, "ntrans": 1},
         "roofline": roof,
         "roofline_kernel": kname,
-        "f64": ({"value": n_units / r64["sec"], "ms_per_step": r64["sec"] * 1e3, "steps": r64["steps"], "eps": 1e-9}
+        "f64": ({"value": n_units / r64["sec"], "ms_per_step": r64["sec"] * 1e3, "steps": r64["steps"], "eps": 1e-9,
+                 "roofline": roofline_entry(r64["stats"], "f64", mode=head_mode)[1],
+                 "roofline_kernel": roofline_entry(r64["stats"], "f64", mode=head_mode)[0]}
                 if r64 else None),
         "f32_over_f64": r64["sec"] / r32["sec"] if r64 else None,
         "plan_seconds": {d: results[d]["plan_s"] for d in results},
