@@ -699,22 +699,34 @@ __device__ __forceinline__ void cis_rev(double t, double &c, double &s)
 
 // exp(2 pi i t) in float64 from a table of exp(2 pi i k / kCisTab) (float64,
 // filled on the host) and the Taylor terms of the remainder: with u =
-// kCisTab frac(t), k = rint(u) and f = u - k in [-1/2, 1/2], t = (k + f) /
-// kCisTab modulo one turn and exp(2 pi i t) = tab[k mod kCisTab] exp(i theta),
-// theta = 2 pi f / kCisTab, |theta| <= pi / kCisTab; sin theta ~ theta -
-// theta^3 / 6 and cos theta ~ 1 - theta^2 / 2 + theta^4 / 24 leave a
-// truncation below theta^5 / 120 = 2.3e-15 (kCisTab = 1024).  The fraction,
-// the scaling by a power of two and the split u = k + f are exact.
+// kCisTab t, k = rint(u) and f = u - k in [-1/2, 1/2], exp(2 pi i t) =
+// tab[k mod kCisTab] exp(i theta), theta = 2 pi f / kCisTab, |theta| <= pi /
+// kCisTab; sin theta ~ theta - theta^3 / 6 and cos theta ~ 1 - theta^2 / 2 +
+// theta^4 / 24 leave a truncation below theta^5 / 120 = 2.3e-15 (kCisTab =
+// 1024), the scale 2 pi / kCisTab folded into the coefficients.  k comes from
+// one add of 1.5 2^52, which rounds u to an integer in round-to-nearest and
+// leaves k + 2^51 in the low bits of the sum's mantissa (|u| < 2^51, i.e.
+// |t| < 2^41 turns); the scaling by a power of two and the split u = k + f
+// are exact.
 __device__ __forceinline__ void cis_tab(double t, const double2 *tab, double &c, double &s)
 {
     static_assert((kCisTab & (kCisTab - 1)) == 0, "power-of-two table");
-    const double u = __builtin_amdgcn_fract(t) * kCisTab;   // [0, kCisTab)
-    const double kf = rint(u);                               // [0, kCisTab]; kCisTab wraps to entry 0
-    const double th = (u - kf) * (6.283185307179586476925287 / kCisTab);
-    const double th2 = th * th;
-    const double sn = fma(th * th2, -1.0 / 6.0, th);
-    const double cs = fma(th2, fma(th2, 1.0 / 24.0, -0.5), 1.0);
-    const double2 e = tab[static_cast<int>(kf) & (kCisTab - 1)];
+    constexpr double kRound = 6755399441055744.0;                 // 1.5 * 2^52
+    constexpr double a1 = 6.283185307179586476925287 / kCisTab;   // theta = a1 f
+    constexpr double a3 = -a1 * a1 * a1 / 6.0, b2 = -a1 * a1 / 2.0, b4 = a1 * a1 * a1 * a1 / 24.0;
+    double u, m;
+    {
+        // separate multiply and add (no contraction): a fused form would need the
+        // 1.5 2^52 addend in a vector register per term
+#pragma clang fp contract(off)
+        u = t * static_cast<double>(kCisTab);
+        m = u + kRound;
+    }
+    const double f = u - (m - kRound);                             // [-1/2, 1/2]
+    const double2 e = tab[__double2loint(m) & (kCisTab - 1)];       // k + 2^51 = k mod kCisTab
+    const double f2 = f * f;
+    const double sn = f * fma(f2, a3, a1);
+    const double cs = fma(f2, fma(f2, b4, b2), 1.0);
     c = fma(e.x, cs, -e.y * sn);
     s = fma(e.y, cs, e.x * sn);
 }
