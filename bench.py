@@ -179,13 +179,13 @@ ALG_OPS_PER_TERM = 30.0
 # sine and cosine and the rotation by the table entry (shared), then one
 # complex multiply-accumulate per row.  Each is one lane-operation per lane.
 VALU_OPS_PER_TERM = {("f32", 1): 89 / 8, ("f32", 2): 121 / 16, ("f32", 3): 153 / 24, ("f32", 4): 185 / 32,
-                     ("f64", 1): 194 / 8, ("f64", 2): 226 / 16, ("f64", 3): 258 / 24, ("f64", 4): 290 / 32}
+                     ("f64", 1): 178 / 8, ("f64", 2): 210 / 16, ("f64", 3): 242 / 24, ("f64", 4): 274 / 32}
 # Lane-cycles per term-row of the same loops at the per-class issue rates
 # (float32 arithmetic 1/2 cycle, hardware sine / cosine 2, the rest 1): float32
 # 32 / 64 / 96 / 128 float32 + 16 transcendental + 41 other per 8 / 16 / 24 / 32
 # term-rows; float64 has no float32 or transcendental instructions.
 VALU_CYCLES_PER_TERM = {("f32", 1): 89 / 8, ("f32", 2): 105 / 16, ("f32", 3): 121 / 24, ("f32", 4): 137 / 32,
-                        ("f64", 1): 194 / 8, ("f64", 2): 226 / 16, ("f64", 3): 258 / 24, ("f64", 4): 290 / 32}
+                        ("f64", 1): 178 / 8, ("f64", 2): 210 / 16, ("f64", 3): 242 / 24, ("f64", 4): 274 / 32}
 
 
 def host_cpu_model() -> str:

@@ -502,11 +502,11 @@ double pair_direct_seconds(int64_t ns, int64_t nt, int dtype)
 // Cost of `rows` data rows relative to one: the direct kernel evaluates each
 // phase factor once for up to kRowBatch rows, so every further row of a group
 // adds only its multiply-adds (about 2 of the 11 issue cycles of a float32
-// term and 4 of the 24 of a float64 term, from the direct kernel's inner-loop
+// term and 4 of the 22 of a float64 term, from the direct kernel's inner-loop
 // instruction counts); a NUFFT sub-problem repeats every stage per row.
 double direct_rows_factor(int rows, int dtype)
 {
-    const double extra = dtype == HVOX_F64 ? 4.0 / 24.25 : 2.0 / 11.125;
+    const double extra = dtype == HVOX_F64 ? 4.0 / 22.25 : 2.0 / 11.125;
     double f = 0.0;
     for (int r = rows; r > 0; r -= kRowBatch) f += 1.0 + extra * (std::min(r, kRowBatch) - 1);
     return f;
