@@ -309,7 +309,7 @@ def main():
     ap.add_argument("--modes", default="",
                     help="comma-separated subset of the runs reported beside the headline (forced_nufft, all_direct, "
                          "batched_ntrans4, forced_nufft_ntrans4, dense_10km, dense_10km_all_direct, dense_30km, "
-                         "sparse_100km, sparse_100km_forced_nufft, compact_f64, lofar_f32); default all")
+                         "sparse_100km, sparse_100km_forced_nufft, compact_f64, compact_f32, lofar_f32); default all")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the runs reported beside the headline (forced NUFFT, all direct, four rows, the dense "
                          "mesh, serving)")
@@ -397,7 +397,8 @@ def main():
     wanted = set(filter(None, args.modes.split(","))) or {"forced_nufft", "all_direct", "batched_ntrans4",
                                                            "dense_10km", "dense_10km_all_direct", "dense_30km",
                                                            "sparse_100km", "sparse_100km_forced_nufft",
-                                                           "forced_nufft_ntrans4", "compact_f64", "lofar_f32"}
+                                                           "forced_nufft_ntrans4", "compact_f64", "compact_f32",
+                                                           "lofar_f32"}
     if not args.no_modes:
         # the two other execution modes of the float32 transform: every sub-problem as a
         # NUFFT (the path the spread / FFT / interp rooflines describe), every one direct
@@ -437,12 +438,15 @@ def main():
         if "sparse_100km_forced_nufft" in wanted:
             modes["sparse_100km_forced_nufft"] = run_mode("f32", 1e-4, 0.0, 5, 1, work=sparse)
         del sparse
-    if not (args.no_modes or dense_head) and "compact_f64" in wanted:
+    if not (args.no_modes or dense_head) and wanted & {"compact_f64", "compact_f32"}:
         # the small float64 case (2,000 vis x 3,072 pix, eps = 1e-6), timed beside the
         # oracle's full sums in the CPU leg
         compact = W.compact_disk()
         log(f"workload {compact.name}")
-        modes["compact_f64"] = run_mode("f64", 1e-6, args.direct_threshold, 20, 2, work=compact)
+        if "compact_f64" in wanted:
+            modes["compact_f64"] = run_mode("f64", 1e-6, args.direct_threshold, 20, 2, work=compact)
+        if "compact_f32" in wanted:   # the same case in float32 at eps = 1e-4
+            modes["compact_f32"] = run_mode("f32", 1e-4, args.direct_threshold, 20, 2, work=compact)
         del compact
     if not (args.no_modes or dense_head) and "lofar_f32" in wanted and not args.lofar:
         # the LOFAR-like wide field (5.0M vis x 4M pix, 60-degree cap), one float32 step
@@ -555,7 +559,7 @@ def main():
         for m, r in modes.items():
             if r["wl"] is wl:
                 out["modes"][m]["rel_l2_vs_oracle"] = errs(r["V"][rv], r["I"][rp], Vs[0], Is[0], len(rv))
-            elif m == "compact_f64":
+            elif m in ("compact_f64", "compact_f32"):
                 # every output row, and the oracle's own time for the whole step
                 ow = r["wl"]
                 t0 = time.perf_counter()
