@@ -367,6 +367,83 @@ __global__ __launch_bounds__(256) void k_spread(const PairDev *__restrict__ pair
 // ---------------------------------------------------------------------------
 // FFT passes (type-3 step 2: pre-correction + zero-padded FFT on grid 2).
 // ---------------------------------------------------------------------------
+// exp(2 pi i k / R) as (cos, sin), evaluated by the compiler: the angle is
+// folded into [0, pi/4] with the quarter-turn and complement symmetries
+// (integer arithmetic, exact) and the Taylor series summed there (eleven terms
+// at |x| <= pi/4 leave a truncation below 1e-22).
+constexpr double kPiRoots = 3.14159265358979323846;
+constexpr double taylor_sin(double x)
+{
+    double t = x, s = x;
+    for (int i = 1; i < 12; ++i) { t *= -x * x / ((2.0 * i) * (2.0 * i + 1.0)); s += t; }
+    return s;
+}
+constexpr double taylor_cos(double x)
+{
+    double t = 1.0, s = 1.0;
+    for (int i = 1; i < 12; ++i) { t *= -x * x / ((2.0 * i - 1.0) * (2.0 * i)); s += t; }
+    return s;
+}
+template <int R> struct Roots {
+    double c[R], s[R];
+    constexpr Roots() : c(), s()
+    {
+        for (int k = 0; k < R; ++k) {
+            const int q = (4 * k) / R, r = 4 * k - q * R;   // angle (pi/2)(q + r/R), 0 <= r < R
+            double cr = 0.0, sr = 0.0;
+            if (2 * r <= R) { const double x = kPiRoots / 2 * r / R; cr = taylor_cos(x); sr = taylor_sin(x); }
+            else { const double x = kPiRoots / 2 * (R - r) / R; cr = taylor_sin(x); sr = taylor_cos(x); }
+            for (int i = 0; i < q; ++i) { const double t = cr; cr = -sr; sr = t; }   // q quarter turns
+            c[k] = cr;
+            s[k] = sr;
+        }
+    }
+};
+
+template <typename T, int R> __device__ __forceinline__ void dft_small(cplx<T> *u, T s);
+
+// R1 R2-point DFT in registers (Cooley-Tukey, one level): input q = R2 q1 + q2,
+// output m = m1 + R1 m2.  An R1-point DFT over q1 for every q2, the twiddle
+// w^(q2 m1) with w = exp(s 2 pi i / (R1 R2)), then an R2-point DFT over q2 for
+// every m1.
+template <typename T, int R1, int R2>
+__device__ __forceinline__ void dft_two_factor(cplx<T> *u, T s)
+{
+    constexpr int R = R1 * R2;
+    constexpr Roots<R> W{};
+    cplx<T> t[R2][R1];
+#pragma unroll
+    for (int q2 = 0; q2 < R2; ++q2) {
+#pragma unroll
+        for (int q1 = 0; q1 < R1; ++q1) t[q2][q1] = u[R2 * q1 + q2];
+        dft_small<T, R1>(t[q2], s);
+#pragma unroll
+        for (int m1 = 1; m1 < R1; ++m1) {
+            const int k = (q2 * m1) % R;
+            if (k == 0) continue;
+            if ((4 * k) % R == 0) {   // a quarter turn: exact
+                const int qt = 4 * k / R;
+                t[q2][m1] = qt == 1 ? cmuli<T>(t[q2][m1], s)
+                          : qt == 2 ? mk<T>(-t[q2][m1].x, -t[q2][m1].y) : cmuli<T>(t[q2][m1], -s);
+            } else {
+                const T c = T(W.c[k]), sn = s * T(W.s[k]);
+                const cplx<T> a = t[q2][m1];
+                t[q2][m1] = mk<T>(a.x * c - a.y * sn, a.y * c + a.x * sn);
+            }
+        }
+    }
+#pragma unroll
+    for (int m1 = 0; m1 < R1; ++m1) {
+        cplx<T> b[R2];
+#pragma unroll
+        for (int q2 = 0; q2 < R2; ++q2) b[q2] = t[q2][m1];
+        dft_small<T, R2>(b, s);
+#pragma unroll
+        for (int m2 = 0; m2 < R2; ++m2) u[m1 + R1 * m2] = b[m2];
+    }
+}
+
+// In-place R-point DFT u_m <- sum_q u_q exp(s 2 pi i q m / R), s = +-1.
 template <typename T, int R>
 __device__ __forceinline__ void dft_small(cplx<T> *u, T s)
 {
@@ -407,7 +484,10 @@ __device__ __forceinline__ void dft_small(cplx<T> *u, T s)
         u[6] = csub<T>(e[2], o2);
         u[3] = cadd<T>(e[3], o3);
         u[7] = csub<T>(e[3], o3);
-    } else {   // R == 5
+    } else if constexpr (R == 9) {
+        dft_two_factor<T, 3, 3>(u, s);
+    } else {
+        static_assert(R == 5, "radix");
         const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
         const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);
         cplx<T> t1 = cadd<T>(u[1], u[4]), t2 = cadd<T>(u[2], u[3]);
@@ -428,25 +508,31 @@ __device__ __forceinline__ void dft_small(cplx<T> *u, T s)
 // place: every thread first reads and transforms its butterflies into
 // registers, then (after a barrier) writes them back in autosorted order.
 // Butterfly i of a line: k = i mod p, inputs x[i + q n/R] twiddled by
-// w^(k q n / (p R)), outputs at (i - k) R + k + m p.
-template <typename T, int R, int NT>
-__device__ void fft_stage(cplx<T> *lds, int nl, int n, int ls, int p, const cplx<T> *tw, T s)
+// w^(k q n / (p R)), outputs at (i - k) R + k + m p.  The first stage
+// (FIRST, p = 1) has k = 0: no twiddles.
+template <typename T, int R, int NT, bool FIRST>
+__device__ __forceinline__ void fft_stage(cplx<T> *lds, int nl, int n, int ls, int p, const cplx<T> *tw, T s)
 {
     constexpr int MAXB = (fft_elems(NT) / R + NT - 1) / NT;
     const int nbf = n / R;
     const int total = nl * nbf;
-    const int twstep = small_div(n, small_rcp(p * R));   // exact: p R divides n
+    const int twstep = FIRST ? 0 : small_div(n, small_rcp(p * R));   // exact: p R divides n
     const int pR = p * R;
-    const float rnbf = small_rcp(nbf), rp = small_rcp(p);
+    const float rnbf = small_rcp(nbf), rp = FIRST ? 1.0f : small_rcp(p);
     cplx<T> v[MAXB][R];
     int obase[MAXB];
+    // the thread index, opaque to the optimiser: otherwise the butterfly
+    // indices of every radix case are hoisted out of the loop over stages and
+    // held in registers across it (64 VGPRs, which halved the occupancy)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
 #pragma unroll
     for (int c = 0; c < MAXB; ++c) {
-        const int b = threadIdx.x + c * NT;
+        const int b = tid + c * NT;
         obase[c] = -1;
         if (b < total) {
             const int j = small_div(b, rnbf), i = b - __mul24(j, nbf);
-            const int g = small_div(i, rp), k = i - __mul24(g, p);
+            const int g = FIRST ? i : small_div(i, rp), k = FIRST ? 0 : i - __mul24(g, p);
             const int lb = __mul24(j, ls);   // line j starts at j * ls in LDS
             obase[c] = lb + __mul24(g, pR) + k;
             const int tk = __mul24(k, twstep);
@@ -454,7 +540,7 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int ls, int p, const cplx
             for (int q = 0; q < R; ++q) {
                 cplx<T> u = lds[lb + i + __mul24(q, nbf)];
                 // exponent q k twstep < n; the LDS table holds exp(s 2 pi i j/n), j < n
-                if (q > 0) u = cmul<T>(u, tw[__mul24(q, tk)]);
+                if (!FIRST && q > 0) u = cmul<T>(u, tw[__mul24(q, tk)]);
                 v[c][q] = u;
             }
             dft_small<T, R>(v[c], s);
@@ -469,6 +555,20 @@ __device__ void fft_stage(cplx<T> *lds, int nl, int n, int ls, int p, const cplx
         }
     }
     __syncthreads();
+}
+
+// A stage of any of the planner's radices (2, 3, 4, 5, 8, 9).
+template <typename T, int NT, bool FIRST>
+__device__ __forceinline__ void fft_stage_radix(int R, cplx<T> *lds, int nl, int n, int ls, int p, const cplx<T> *tw, T s)
+{
+    switch (R) {
+    case 9: fft_stage<T, 9, NT, FIRST>(lds, nl, n, ls, p, tw, s); break;
+    case 8: fft_stage<T, 8, NT, FIRST>(lds, nl, n, ls, p, tw, s); break;
+    case 5: fft_stage<T, 5, NT, FIRST>(lds, nl, n, ls, p, tw, s); break;
+    case 4: fft_stage<T, 4, NT, FIRST>(lds, nl, n, ls, p, tw, s); break;
+    case 3: fft_stage<T, 3, NT, FIRST>(lds, nl, n, ls, p, tw, s); break;
+    default: fft_stage<T, 2, NT, FIRST>(lds, nl, n, ls, p, tw, s); break;
+    }
 }
 
 // One axis pass for every sub-problem of a batch.  Element e of an input
@@ -601,11 +701,8 @@ __global__ __launch_bounds__(NT) void k_fft_pass(const PairDev *__restrict__ pai
     int pc = 1;
     for (int st = 0; st < P.nrad[pass]; ++st) {
         const int R = P.radix[pass][st];
-        if (R == 8) fft_stage<T, 8, NT>(lds, nl, n, ls, pc, ltw, s);
-        else if (R == 4) fft_stage<T, 4, NT>(lds, nl, n, ls, pc, ltw, s);
-        else if (R == 2) fft_stage<T, 2, NT>(lds, nl, n, ls, pc, ltw, s);
-        else if (R == 3) fft_stage<T, 3, NT>(lds, nl, n, ls, pc, ltw, s);
-        else fft_stage<T, 5, NT>(lds, nl, n, ls, pc, ltw, s);
+        if (st == 0) fft_stage_radix<T, NT, true>(R, lds, nl, n, ls, pc, ltw, s);
+        else fft_stage_radix<T, NT, false>(R, lds, nl, n, ls, pc, ltw, s);
         pc *= R;
     }
     // kept window: wstart is 0 (whole line) or -R with 2R < n, so wstart + q lies in (-n, n)

@@ -108,17 +108,53 @@ int32_t smooth_even(int64_t n)
     }
 }
 
-// Radix stages of an n-point FFT: 8s, then a 4 or a 2, then 3s, then 5s.
+// Radix stages of an n-point FFT (n = 2^a 3^b 5^c): the product of radices
+// from {2, 3, 4, 5, 8, 9} with the least estimated VALU work per element,
+// largest radix first (the first stage has no twiddles).  Every stage costs a
+// butterfly of R elements ~35 instructions of index and LDS address
+// arithmetic, two LDS operations per element, ~6 per twiddle product and the
+// butterfly's own arithmetic (the radix-8 stage, 123 instructions in the
+// gfx950 assembly, fixes the scale), so fewer, larger stages win.  Radices 6,
+// 10, 12 and 16 measured slower: their butterflies' registers cost occupancy.
 int factor_radices(int32_t n, uint8_t *radix)
 {
-    int ns = 0;
+    struct Rad { int r, e2, e3, e5, arith; };
+    static const Rad rads[] = {{9, 0, 2, 0, 120}, {8, 3, 0, 0, 60}, {5, 0, 0, 1, 40},
+                               {4, 2, 0, 0, 16},  {3, 0, 1, 0, 16}, {2, 1, 0, 0, 4}};
+    constexpr int kRads = static_cast<int>(sizeof(rads) / sizeof(rads[0]));
+    int a = 0, b = 0, c = 0;
     int32_t m = n;
-    while (m % 8 == 0) { if (ns >= kMaxStages) return -1; radix[ns++] = 8; m /= 8; }
-    while (m % 4 == 0) { if (ns >= kMaxStages) return -1; radix[ns++] = 4; m /= 4; }
-    while (m % 2 == 0) { if (ns >= kMaxStages) return -1; radix[ns++] = 2; m /= 2; }
-    while (m % 3 == 0) { if (ns >= kMaxStages) return -1; radix[ns++] = 3; m /= 3; }
-    while (m % 5 == 0) { if (ns >= kMaxStages) return -1; radix[ns++] = 5; m /= 5; }
+    if (m < 1) return -1;
+    while (m % 2 == 0) { m /= 2; ++a; }
+    while (m % 3 == 0) { m /= 3; ++b; }
+    while (m % 5 == 0) { m /= 5; ++c; }
     if (m != 1) return -1;
+    // best[a][b][c]: least cost per element of a 2^a 3^b 5^c-point FFT, and the radix taken first
+    const int A = a + 1, B = b + 1, C = c + 1;
+    std::vector<double> best(static_cast<size_t>(A) * B * C, 1e300);
+    std::vector<int> pick(best.size(), -1);
+    auto at = [&](int x, int y, int z) { return (static_cast<size_t>(x) * B + y) * C + z; };
+    best[at(0, 0, 0)] = 0.0;
+    for (int x = 0; x <= a; ++x)
+        for (int y = 0; y <= b; ++y)
+            for (int z = 0; z <= c; ++z) {
+                if (x + y + z == 0) continue;
+                for (int i = 0; i < kRads; ++i) {
+                    const Rad &q = rads[i];
+                    if (q.e2 > x || q.e3 > y || q.e5 > z) continue;
+                    const double rest = best[at(x - q.e2, y - q.e3, z - q.e5)];
+                    const double cost = rest + (35.0 + 2.0 * q.r + 6.0 * (q.r - 1) + q.arith) / q.r;
+                    if (cost < best[at(x, y, z)]) { best[at(x, y, z)] = cost; pick[at(x, y, z)] = i; }
+                }
+            }
+    int ns = 0;
+    for (int x = a, y = b, z = c; x + y + z > 0;) {
+        if (ns >= kMaxStages) return -1;
+        const Rad &q = rads[pick[at(x, y, z)]];
+        radix[ns++] = static_cast<uint8_t>(q.r);
+        x -= q.e2; y -= q.e3; z -= q.e5;
+    }
+    std::sort(radix, radix + ns, [](uint8_t u, uint8_t v) { return u > v; });
     for (int i = ns; i < kMaxStages; ++i) radix[i] = 0;
     return ns;
 }

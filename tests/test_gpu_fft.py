@@ -48,7 +48,8 @@ def _need_gpu():
 
 
 @pytest.mark.parametrize("dtype,tol", [("f32", 2e-6), ("f64", 1e-13)])
-@pytest.mark.parametrize("n", [2, 6, 12, 30, 64, 100, 250, 486, 1000, 2048, 2160, 4096])
+@pytest.mark.parametrize("n", [2, 6, 12, 30, 36, 64, 100, 250, 432, 486, 810, 1000, 1152, 1250, 1296, 2048, 2160,
+                               3000, 3888, 4096])
 def test_fft_full_window(dtype, tol, n):
     rng = np.random.default_rng(n)
     nlines = 5 if n > 1000 else 37
