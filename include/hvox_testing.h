@@ -29,6 +29,16 @@ extern "C" {
 int hvox_test_fft(int32_t dtype, int32_t n, int32_t nin, int32_t nlines, int32_t wstart, int32_t wcount,
                   int32_t sign, const void *in, void *out, void *stream);
 
+/*
+ * The radix plan of the FFT passes for lines of n points (the stages of the
+ * FFT step of HVOX Sect. 3): writes the radix of every Stockham stage, first
+ * stage first, to radix[0 .. k-1] and returns k (at most 16), or a negative
+ * HVOX error code when n is odd, not 2-3-5 smooth or beyond 4096.  radix is a
+ * host buffer of at least 16 bytes owned by the caller.  Host code only: no
+ * GPU is needed.
+ */
+int hvox_test_fft_radices(int32_t n, uint8_t *radix);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1278,3 +1278,15 @@ extern "C" int hvox_test_fft(int32_t dtype, int32_t n, int32_t nin, int32_t nlin
     if (e != hipSuccess) return fail(HVOX_ERR_HIP, std::string("HIP: ") + hipGetErrorString(e));
     return HVOX_OK;
 }
+
+extern "C" int hvox_test_fft_radices(int32_t n, uint8_t *radix)
+{
+    using namespace hvox;
+    if (!radix || n < 2 || n > kFftMaxLen || smooth_even(n) != n)
+        return fail(HVOX_ERR_ARG, "n must be even, 2-3-5 smooth and at most the longest FFT line");
+    uint8_t r[kMaxStages];
+    const int ns = factor_radices(n, r);
+    if (ns < 1) return fail(HVOX_ERR_ARG, "no radix plan for this length");
+    for (int i = 0; i < ns; ++i) radix[i] = r[i];
+    return ns;
+}

@@ -400,3 +400,42 @@ def test_sparse_dcos_sky_is_500_pixels_of_the_rung_grid(radius_km):
     with hv.Plan(wl.uvw, wl.xyz, 1e-4, "f32", host_only=True) as p:
         info = p.info()
     assert info["n_pairs_nufft"] + info["n_pairs_direct"] == info["n_vis_chunks"] * info["n_sky_chunks"]
+
+
+def _radices(n):
+    lib = hv.load_library()
+    f = lib.hvox_test_fft_radices
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8)]
+    buf = (ctypes.c_uint8 * 16)()
+    k = f(n, buf)
+    return k, list(buf[:max(k, 0)])
+
+
+def test_fft_radix_plans():
+    """Every even 2-3-5-smooth line length up to 4096 gets a plan of Stockham
+    stages whose radices multiply to the length, drawn from the butterflies the
+    FFT kernel has (2, 3, 4, 5, 8, 9), largest first (the first stage runs
+    without twiddles); other lengths are refused.  The lengths that carry the
+    SKA-like workload's FFT work take the measured plans."""
+    count = 0
+    for n in range(2, 4097, 2):
+        m = n
+        for p in (2, 3, 5):
+            while m % p == 0:
+                m //= p
+        k, rad = _radices(n)
+        if m != 1:
+            assert k == -1, n                       # HVOX_ERR_ARG
+            continue
+        count += 1
+        assert 1 <= k <= 16, n
+        assert math.prod(rad) == n, (n, rad)
+        assert set(rad) <= {2, 3, 4, 5, 8, 9}, (n, rad)
+        assert rad == sorted(rad, reverse=True), (n, rad)
+    assert count == 110                             # the even 2-3-5-smooth numbers up to 4096
+    for n in (7, 15, 4098, 8192, 0, -4):
+        assert _radices(n)[0] == -1, n
+    assert _radices(1152)[1] == [9, 8, 4, 4]
+    assert _radices(1296)[1] == [9, 9, 4, 4]
+    assert _radices(36)[1] == [9, 4]
