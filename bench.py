@@ -327,7 +327,7 @@ def main():
                     help="only run a plain device copy of MIB mebibytes three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: this build runs the whole transform on a single MI355X "
+        print(f"bench.py measures one GPU only: the library runs the whole transform on a single MI355X "
               f"(--gpus {args.gpus} is not supported)", file=sys.stderr)
         sys.exit(2)
 
