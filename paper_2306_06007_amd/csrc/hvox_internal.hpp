@@ -37,7 +37,7 @@ constexpr int kDirectTile = 512;     // targets per direct-sum workgroup (two pe
 constexpr int kDirectSrcTile = 256;  // sources staged in LDS at a time
 constexpr int kDirectSeg = 8192;     // longest source segment of a direct-sum work item
 constexpr int64_t kDirectMinItems = 4096;   // shorter segments while a plan has fewer direct work items
-constexpr int kDirectWgPerCu = 5;    // direct-sum workgroups per CU while NUFFT work runs beside it
+constexpr int kDirectWgPerCu = 8;    // direct-sum workgroups per CU while NUFFT work runs beside it
 constexpr int kCisTab = 1024;        // entries exp(2 pi i k / kCisTab) of the float64 direct sum's phase table
 constexpr int kRowBatch = 4;         // data rows (ntrans) per direct-sum launch, most per NUFFT pass, accumulator rows
 constexpr int kInterpLanes = 16;     // interp: lanes per target
