@@ -49,9 +49,9 @@ def test_every_line_length(model):
     ("ska", lambda: W.ska_like(n_pix=10000, n_ant=30, n_times=6)),
     ("dense", lambda: W.dense_dcos(1.0)),
     ("compact", lambda: W.compact_disk()),
-])
-@pytest.mark.parametrize("dtype,eps", [(0, 1e-4), (1, 1e-9)])
-@pytest.mark.parametrize("threshold", [-1.0, 0.0])
+], ids=["ska_like", "dense_1km", "compact"])
+@pytest.mark.parametrize("dtype,eps", [(0, 1e-4), (1, 1e-9)], ids=["f32", "f64"])
+@pytest.mark.parametrize("threshold", [-1.0, 0.0], ids=["auto", "forced_nufft"])
 def test_plan_geometries(model, name, make, dtype, eps, threshold):
     tmp, exe = model
     wl = make()
